@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: SHT+ISHT forward and backward fields/s at 721x1440, lmax 720.
+
+One step = one pass of the whole path over the batch: SHT -> ISHT (forward)
+then ISHT^T -> SHT^T (backward), i.e. four transforms of 72 fields on the
+equiangular 721 x 1440 grid (both poles, Clenshaw-Curtis weights),
+lmax = mmax = 720.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  Besides the driver's contract fields it carries:
+  roofline     -- the dominant kernel (Legendre contraction), algorithmic
+                  flops per launch / its average launch time from HIP events
+                  recorded on the launch stream during the timed region;
+  cpu_baseline -- the FP64 NumPy oracle doing the same four transforms on the
+                  host (rank 0, N = 1), with its thread count;
+  err_vs_fp64  -- relative L2 of the SHT output against the oracle on the
+                  same float32 input.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SHT+ISHT fwd+bwd fields/sec at 721×1440 lmax720; % roofline; err vs FP64"
+PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0, "bf16x3": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "bf16x2", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fields", type=int, default=72,
+                    help="fields in the oracle's timed sample (of the 72)")
+    return ap.parse_args()
+
+
+def legendre_flops(nlat, lmax, mmax, fields):
+    """Multiply-adds x 2 of one folded Legendre contraction launch: every
+    (l, m) pair with m <= l meets the nk = (nlat+1)/2 northern rings once per
+    real column (2 per field)."""
+    nk = (nlat + 1) // 2
+    pairs = sum(lmax - m for m in range(mmax))
+    return 2.0 * pairs * nk * 2 * fields
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+              "fields are independent, so N GPUs would each run this single-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2507_12144_amd as P
+
+    torch.cuda.set_device(0)
+    nlat, nlon, L, M, B, C = 721, 1440, 720, 720, 1, 72
+    F = B * C
+    t0 = time.perf_counter()
+    plan = P.Plan(dict(nlat=nlat, nlon=nlon, lmax=L, mmax=M, grid="equiangular", batch=B, channels=C),
+                  precision=args.precision)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+
+    # synthetic input: band-limited field (seed 0) + 1e-3 white-noise probe (seed 1)
+    a = torch.from_numpy(synth.coefficients(0, B, C, L, M).astype(np.complex64)).cuda()
+    probe = torch.from_numpy(synth.white_noise(1, (B, C, nlat, nlon)).astype(np.float32)).cuda()
+    u = plan.isht(a)
+    u.add_(probe)
+    y = torch.empty(plan.spec_shape(), dtype=torch.complex64, device="cuda")
+    x2 = torch.empty(plan.grid_shape(), dtype=torch.float32, device="cuda")
+    gy = torch.empty_like(y)
+    gx = torch.empty_like(x2)
+
+    def step():
+        plan.sht(u, out=y)
+        plan.isht(y, out=x2)
+        plan.isht_T(x2, out=gy)
+        plan.sht_T(gy, out=gx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    plan.set_timing(True)
+    plan.read_timing()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_timing(False)
+    kernels = plan.read_timing()
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / args.steps
+    value = F * args.steps / wall
+
+    # roofline of the dominant kernel
+    ana_ms, ana_n = kernels["legendre_analysis"]
+    syn_ms, syn_n = kernels["legendre_synthesis"]
+    kind, tot, n = ("legendre_analysis", ana_ms, ana_n) if ana_ms >= syn_ms else ("legendre_synthesis", syn_ms, syn_n)
+    flops = legendre_flops(nlat, L, M, F)
+    avg_s = tot / max(n, 1) * 1e-3
+    peak = PEAKS_TFLOPS[args.precision]
+    achieved = flops / avg_s / 1e12
+    roofline = {"bound": "mfma", "kernel": kind, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_flops_per_launch": flops}
+    per_kernel_us = {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in kernels.items() if v[1]}
+
+    # accuracy of this run's SHT against the FP64 oracle; CPU baseline timing
+    err = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            blas_threads = max([i.get("num_threads", 0) for i in threadpool_info()] or [0])
+        except Exception:
+            blas_threads = 0
+        nf = max(1, min(args.cpu_fields, F))
+        u_host = u.cpu().numpy().astype(np.float64)[:, :nf]
+        t0 = time.perf_counter()
+        ry = oracle.sht(u_host, L, M, 0)
+        rx = oracle.isht(ry, nlat, nlon, 0)
+        rgy = oracle.isht_T(rx, L, M, 0)
+        oracle.sht_T(rgy, nlat, nlon, 0)
+        cpu_s = time.perf_counter() - t0
+        yg = y.cpu().numpy()[:, :nf]
+        err = float(np.linalg.norm((yg - ry).ravel()) / np.linalg.norm(ry.ravel()))
+        cpu = {"value": round(nf / cpu_s, 3), "unit": "fields/s", "cores": blas_threads or os.cpu_count(),
+               "kind": "oracle",
+               "sample": f"{nf} of the {F} fields, full 721x1440 grid, one SHT->ISHT->ISHT^T->SHT^T pass in "
+                         f"float64 ({cpu_s:.1f} s); os.cpu_count()={os.cpu_count()}, "
+                         f"affinity={len(os.sched_getaffinity(0))}"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": "SHT->ISHT->ISHT^T->SHT^T, equiangular 721x1440 with poles (Clenshaw-Curtis), "
+                               "lmax=mmax=720, batch 1 x 72 channels",
+                   "nlat": nlat, "nlon": nlon, "lmax": L, "mmax": M, "fields": F, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "err_vs_fp64": {"sht_rel_l2": err},
+        "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
+        "kernel_avg_us": per_kernel_us,
+        "plan_build_s": round(plan_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * sht.h -- C ABI of the MI355X (gfx950) real spherical harmonic transform
+ * library (libsht.so).
+ *
+ * The operation is the real SHT pair of App. B.3 of "FourCastNet 3"
+ * (arXiv 2507.12144): analysis (eq. sht) as a ring DFT along longitude
+ * followed by a quadrature-weighted contraction with orthonormal associated
+ * Legendre functions per order m (the decomposition described after
+ * eq. spherical_harmonics and written out in Alg. 1), and synthesis
+ * (eq. isht) running the same two steps in reverse, plus the exact adjoints
+ * of both.  The grids are those of App. B.1.
+ *
+ * Conventions (all functions):
+ *  - lmax and mmax are counts: degrees l < lmax, orders m < mmax (the mode
+ *    truncation xf[..., :mmax] and the mmax x lmax x H tensor L of Alg. 1).
+ *    1 <= mmax <= lmax and 2*mmax <= nlon (the Nyquist bin is never used).
+ *  - Grid tensors (x, gx): float32 [batch][channels][nlat][nlon], C order
+ *    (B x C x H x W of Alg. 1).  Rings run from the north pole southwards;
+ *    longitude j is at 2*pi*j/nlon.
+ *  - Spectral tensors (y, gy): complex64 stored as interleaved float32
+ *    (re, im), [batch][channels][lmax][mmax], m fastest
+ *    (B x C x lmax x mmax of Alg. 1).  Only m >= 0 is stored.
+ *  - sht_forward writes 0 for l < m and an exactly zero imaginary part for
+ *    m = 0; isht_forward and sht_backward ignore those entries of their input.
+ *  - The DFT carries the longitude quadrature 2*pi/nlon (the "2 pi *
+ *    FFT_1D_R2C" step of Alg. 1); the ISHT weights order m >= 1 by 2 (real
+ *    fields: u^_l^{-m} = (-1)^m conj(u^_l^m)).
+ *  - All tensors are DEVICE pointers owned by the caller.  In/out buffers
+ *    must not alias.  With several descriptors (the batching form) each
+ *    buffer is the concatenation of the segments in descriptor order; use
+ *    sht_plan_segment for the element offsets.
+ *  - Calls enqueue work on hip_stream (NULL: the plan's own stream) and
+ *    return without waiting.  A kernel fault surfaces as SHT_ERR_HIP on a
+ *    later call or on the caller's synchronisation.  One stream at a time
+ *    per plan: concurrent calls on one plan from different streams race on
+ *    the plan's workspace.
+ *  - Results are bitwise reproducible for a fixed plan.
+ *  - Argument checks run on the host before any HIP call; no C++ exception
+ *    crosses this interface.  On failure, sht_last_error() returns a
+ *    thread-local description.
+ */
+#ifndef SHT_MI355X_H
+#define SHT_MI355X_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SHT_OK = 0,
+    SHT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, unknown enum        */
+    SHT_ERR_UNSUPPORTED = 2,   /* valid but not implemented (e.g. a prime
+                                  factor > 5 in nlon, nlon > 4096)          */
+    SHT_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed                 */
+    SHT_ERR_HIP = 4,           /* a HIP runtime call failed                  */
+    SHT_ERR_INTERNAL = 5
+} sht_status;
+
+/* Latitude grids (App. B.1). */
+typedef enum {
+    SHT_GRID_EQUIANGULAR = 0,           /* t_k = pi k/(nlat-1), both poles on the
+                                           grid; Clenshaw-Curtis weights (footnote
+                                           to eq. latlon_quad_weights)             */
+    SHT_GRID_GAUSS = 1,                 /* Gauss-Legendre nodes and weights        */
+    SHT_GRID_EQUIANGULAR_TRAPEZOID = 2  /* as 0 with sin(t) dt weights
+                                           (eq. latlon_quad_weights)               */
+} sht_grid;
+
+/* Arithmetic of the Legendre contraction.  The ring DFT is float32 in all
+ * forms; the Legendre table is always produced by a float64 recurrence and
+ * rounded (to nearest even) to the storage form. */
+typedef enum {
+    SHT_PREC_FP32 = 0,   /* float32 table and data, float32 MFMA            */
+    SHT_PREC_BF16 = 1,   /* bfloat16 table and data, bf16 MFMA, fp32 accum   */
+    SHT_PREC_BF16X2 = 2, /* split bf16: v = hi + lo for table and data,
+                            products hi*hi + hi*lo + lo*hi, fp32 accumulate  */
+    SHT_PREC_BF16X3 = 3  /* three-term bf16 split of the table and data,
+                            the six products of order < 3, fp32 accumulate  */
+} sht_precision;
+
+/* One transform shape: batch x channels fields on an nlat x nlon grid. */
+typedef struct {
+    int nlat, nlon, lmax, mmax;
+    sht_grid grid;
+    int batch, channels;
+} sht_desc;
+
+typedef struct sht_plan_s* sht_plan_t;
+
+/* Create a plan for ndesc >= 1 shapes (ndesc > 1: the batching form, in
+ * which every call transforms all segments).  Builds the nodes, weights and
+ * the Legendre table on the device in float64 (App. B.1, eq.
+ * spherical_harmonics), allocates the workspace, and leaves the plan bound to
+ * the current HIP device.  hip_stream: the stream used for plan-time work and
+ * as the default stream of later calls (NULL: the null stream).
+ * *out is set to NULL on failure. */
+sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc,
+                    sht_precision prec, void* hip_stream);
+
+/* Synchronise the plan's stream and free everything the plan owns.
+ * NULL is accepted and ignored. */
+sht_status sht_plan_destroy(sht_plan_t plan);
+
+/* Element offsets of segment i inside the concatenated grid buffer (float32
+ * elements) and spectral buffer (complex elements). */
+sht_status sht_plan_segment(sht_plan_t plan, int i, size_t* grid_offset,
+                            size_t* spec_offset);
+
+/* Total number of grid (float32) and spectral (complex) elements over all
+ * segments: the sizes the caller allocates. */
+sht_status sht_plan_sizes(sht_plan_t plan, size_t* grid_elems, size_t* spec_elems);
+
+/* Copy segment i's nodes x_k = cos(t_k) and latitude weights w_k (float64,
+ * nlat each, north to south; sum(w) approximates 2) to HOST arrays. */
+sht_status sht_plan_grid(sht_plan_t plan, int i, double* x_host, double* w_host);
+
+/* Forward SHT (eq. sht on the grid):
+ *   y[l,m] = sum_k sum_j (2 pi/nlon) w_k x[k,j] P^_l^m(x_k) e^{-2 pi i j m/nlon}
+ * x: float32 grid tensor (device, read), y: complex64 spectral tensor
+ * (device, written in full). */
+sht_status sht_forward(sht_plan_t plan, const float* x, void* y, void* hip_stream);
+
+/* Inverse SHT (eq. isht for real fields):
+ *   x[k,j] = sum_{m<mmax} c_m Re(e^{2 pi i j m/nlon} sum_{l=m}^{lmax-1} P^_l^m(x_k) y[l,m]),
+ *   c_0 = 1, c_m = 2.
+ * y: spectral tensor (device, read), x: grid tensor (device, written). */
+sht_status isht_forward(sht_plan_t plan, const void* y, float* x, void* hip_stream);
+
+/* Adjoint of sht_forward under the real inner product Re sum conj(a) b
+ * (PyTorch's complex-gradient convention):
+ *   gx[k,j] = (2 pi/nlon) w_k sum_m Re(e^{2 pi i j m/nlon} sum_l P^_l^m(x_k) gy[l,m])
+ * with weight 1 for every m.  gy: spectral (device, read), gx: grid
+ * (device, written). */
+sht_status sht_backward(sht_plan_t plan, const void* gy, float* gx, void* hip_stream);
+
+/* Adjoint of isht_forward:
+ *   gy[l,m] = c_m sum_k P^_l^m(x_k) sum_j gx[k,j] e^{-2 pi i j m/nlon}  (l >= m), 0 for l < m.
+ * gx: grid (device, read), gy: spectral (device, written in full). */
+sht_status isht_backward(sht_plan_t plan, const float* gx, void* gy, void* hip_stream);
+
+/* Per-degree complex channel mix, a multi-channel form of the spectral
+ * convolution of App. B.4 (eq. s2_spectral_conv), for a plan with one
+ * segment:  out[b,c',l,m] = sum_c W[l,c',c] in[b,c,l,m]  (adjoint != 0: uses
+ * conj(W[l,c,c']) instead, i.e. W_l^H).  W: complex64 [lmax][channels]
+ * [channels] (device), in/out: spectral tensors of the plan's shape (device,
+ * must not alias).  Entries l < m of out are written as 0. */
+sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void* out,
+                           int adjoint, void* hip_stream);
+
+/* Kernel timing (diagnostics).  With enable != 0 every later call on the
+ * plan records a pair of HIP events on the call's stream around each kernel
+ * it launches.  sht_plan_timing_read waits for the recorded events, adds the
+ * elapsed milliseconds and launch counts per kernel kind into ms[i] and
+ * counts[i] for i < nkinds (kinds: 0 ring DFT forward, 1 ring DFT inverse,
+ * 2 Legendre analysis, 3 Legendre synthesis, 4 zero fill, 5 channel mix),
+ * then forgets them.  Host arrays; nkinds <= SHT_TIMING_KINDS. */
+#define SHT_TIMING_KINDS 6
+sht_status sht_plan_timing(sht_plan_t plan, int enable);
+sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds);
+
+const char* sht_status_string(sht_status s);
+const char* sht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_MI355X_H */

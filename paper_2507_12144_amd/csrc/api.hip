@@ -1,0 +1,525 @@
+// Host side of libsht.so: argument checks, plan construction (float64 grid and
+// Legendre table on the device), workspace ownership and the C ABI declared
+// in include/sht.h.  Every argument check runs before the first HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sht.h"
+#include "internal.h"
+
+struct sht_plan_s;
+
+namespace sht {
+namespace {
+
+thread_local std::string g_last_error;
+
+sht_status fail(sht_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+sht_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(SHT_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+  return fail(SHT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Test hook: SHT_TEST_FAIL_ALLOC=n makes the n-th device allocation of the
+// process fail with hipErrorOutOfMemory (n >= 1).
+int g_alloc_count = 0;
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  ++g_alloc_count;
+  const char* env = std::getenv("SHT_TEST_FAIL_ALLOC");
+  if (env && std::atoi(env) == g_alloc_count) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  if (bytes == 0) bytes = 256;
+  return hipMalloc(p, bytes);
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool only_small_primes(int n) {
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+Storage storage_of(sht_precision p) {
+  switch (p) {
+    case SHT_PREC_BF16: return Storage::BF16;
+    case SHT_PREC_BF16X2: return Storage::BF16X2;
+    case SHT_PREC_BF16X3: return Storage::BF16X3;
+    default: return Storage::F32;
+  }
+}
+
+size_t storage_bytes_per_entry(Storage s) {
+  switch (s) {
+    case Storage::F32: return 4;
+    case Storage::BF16: return 2;
+    case Storage::BF16X2: return 4;
+    case Storage::BF16X3: return 6;
+  }
+  return 4;
+}
+
+struct Segment {
+  sht_desc d{};
+  SegGeom g{};
+  DftPlan dp{};
+  size_t grid_off = 0, spec_off = 0;
+  double* x = nullptr;
+  double* s = nullptr;
+  double* w = nullptr;
+  float* scale_sht = nullptr;  // (2 pi / nlon) w_k, k < nk
+  float* scale_one = nullptr;  // 1
+  float2* tw = nullptr;        // e^{-2 pi i j / nlon}
+  int64_t* row_off = nullptr;
+  int* rows_pad = nullptr;
+  void* table = nullptr;
+  size_t plane_stride = 0;
+  int4* tiles_ana = nullptr;
+  int n_ana = 0;
+  int4* tiles_syn = nullptr;
+  int n_syn = 0;
+  float* work = nullptr;
+};
+
+sht_status validate_desc(const sht_desc& d, int i) {
+  if (d.nlat < 2 || d.nlon < 2)
+    return fail(SHT_ERR_INVALID_ARG, "desc %d: nlat and nlon must be >= 2 (got %d, %d)", i, d.nlat, d.nlon);
+  if (d.lmax < 1 || d.mmax < 1)
+    return fail(SHT_ERR_INVALID_ARG, "desc %d: lmax and mmax must be >= 1", i);
+  if (d.mmax > d.lmax) return fail(SHT_ERR_INVALID_ARG, "desc %d: mmax > lmax", i);
+  if (2 * static_cast<long long>(d.mmax) > d.nlon)
+    return fail(SHT_ERR_INVALID_ARG, "desc %d: mmax > nlon/2 (the Nyquist bin is never used)", i);
+  if (d.batch < 1 || d.channels < 1)
+    return fail(SHT_ERR_INVALID_ARG, "desc %d: batch and channels must be >= 1", i);
+  if (d.grid != SHT_GRID_EQUIANGULAR && d.grid != SHT_GRID_GAUSS && d.grid != SHT_GRID_EQUIANGULAR_TRAPEZOID)
+    return fail(SHT_ERR_INVALID_ARG, "desc %d: unknown grid %d", i, static_cast<int>(d.grid));
+  if (d.nlon > kMaxNlon) return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlon > %d", i, kMaxNlon);
+  if (!only_small_primes(d.nlon))
+    return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlon = %d has a prime factor > 5", i, d.nlon);
+  const long long F = static_cast<long long>(d.batch) * d.channels;
+  if (F > (1LL << 24) || static_cast<long long>(d.nlat) > (1 << 20) || d.lmax > (1 << 16))
+    return fail(SHT_ERR_UNSUPPORTED, "desc %d: sizes beyond the supported range", i);
+  return SHT_OK;
+}
+
+}  // namespace
+}  // namespace sht
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+struct sht_plan_s {
+  std::vector<sht::Segment> segs;
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> event_pool;
+  sht_precision prec = SHT_PREC_FP32;
+  sht::Storage storage = sht::Storage::F32;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t grid_elems = 0, spec_elems = 0;
+};
+
+namespace sht {
+namespace {
+
+void free_segment(Segment& s) {
+  void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.row_off, s.rows_pad, s.table,
+                  s.tiles_ana, s.tiles_syn, s.work};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  s = Segment{};
+}
+
+__global__ void ring_scale_kernel(int nk, int nlon, const double* __restrict__ w, float* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nk) out[k] = static_cast<float>(2.0 * 3.14159265358979323846 / nlon * w[k]);
+}
+
+template <typename T>
+sht_status upload(T** dst, const std::vector<T>& v, hipStream_t st, const char* what) {
+  hipError_t e = dev_alloc(reinterpret_cast<void**>(dst), v.size() * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, what);
+  e = hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, what);
+  // the host vector dies with the caller's frame: finish the copy now
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return SHT_OK;
+}
+
+sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStream_t st) {
+  S.d = d;
+  SegGeom& g = S.g;
+  g.nlat = d.nlat;
+  g.nlon = d.nlon;
+  g.lmax = d.lmax;
+  g.mmax = d.mmax;
+  g.F = d.batch * d.channels;
+  g.nk = (d.nlat + 1) / 2;
+  g.has_equator = (d.nlat % 2) == 1;
+  g.kpad = static_cast<int>(round_up(g.nk, kRingPad));
+  g.npad = static_cast<int>(round_up(2 * static_cast<size_t>(g.F), kColPad));
+  if (!make_dft_plan(d.nlon, &S.dp)) return fail(SHT_ERR_UNSUPPORTED, "nlon = %d cannot be factored", d.nlon);
+
+  hipError_t e;
+  sht_status rc;
+  // nodes and weights, float64 on the device
+  for (double** p : {&S.x, &S.s, &S.w}) {
+    e = dev_alloc(reinterpret_cast<void**>(p), sizeof(double) * d.nlat);
+    if (e != hipSuccess) return hip_fail(e, "grid allocation");
+  }
+  e = launch_grid(d.nlat, static_cast<int>(d.grid), S.x, S.s, S.w, st);
+  if (e != hipSuccess) return hip_fail(e, "grid kernel");
+  e = dev_alloc(reinterpret_cast<void**>(&S.scale_sht), sizeof(float) * g.nk);
+  if (e != hipSuccess) return hip_fail(e, "ring scale allocation");
+  hipLaunchKernelGGL(ring_scale_kernel, dim3((g.nk + 63) / 64), dim3(64), 0, st, g.nk, d.nlon, S.w,
+                     S.scale_sht);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "ring scale kernel");
+  if ((rc = upload(&S.scale_one, std::vector<float>(g.nk, 1.0f), st, "ring scale upload")) != SHT_OK) return rc;
+
+  // twiddles e^{-2 pi i j / n} in float64, rounded once
+  std::vector<float2> tw(d.nlon);
+  for (int j = 0; j < d.nlon; ++j) {
+    const double a = -2.0 * M_PI * static_cast<double>(j) / d.nlon;
+    tw[j] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+  }
+  if ((rc = upload(&S.tw, tw, st, "twiddle upload")) != SHT_OK) return rc;
+
+  // folded table layout: per m two parity blocks of rows_pad[m] rows
+  std::vector<int64_t> row_off(d.mmax);
+  std::vector<int> rows_pad(d.mmax);
+  int64_t rows = 0;
+  std::vector<int4> ana, syn;
+  for (int m = 0; m < d.mmax; ++m) {
+    const int n0 = (d.lmax - m + 1) / 2;
+    const int n1 = (d.lmax - m) / 2;
+    rows_pad[m] = static_cast<int>(round_up(n0 > 0 ? n0 : 1, kRowPad));
+    row_off[m] = rows;
+    rows += 2LL * rows_pad[m];
+    for (int p = 0; p < 2; ++p) {
+      const int np = p == 0 ? n0 : n1;
+      for (int r = 0; r < np; r += 64) ana.push_back(make_int4(m, p, r, 0));
+      if (np > 0)
+        for (int k = 0; k < g.kpad; k += 64) syn.push_back(make_int4(m, p, k, 0));
+    }
+  }
+  if ((rc = upload(&S.row_off, row_off, st, "table offsets")) != SHT_OK) return rc;
+  if ((rc = upload(&S.rows_pad, rows_pad, st, "table offsets")) != SHT_OK) return rc;
+  if ((rc = upload(&S.tiles_ana, ana, st, "tile list")) != SHT_OK) return rc;
+  if ((rc = upload(&S.tiles_syn, syn, st, "tile list")) != SHT_OK) return rc;
+  S.n_ana = static_cast<int>(ana.size());
+  S.n_syn = static_cast<int>(syn.size());
+
+  const size_t entries = static_cast<size_t>(rows) * g.kpad;
+  S.plane_stride = entries;
+  const size_t tbytes = entries * storage_bytes_per_entry(storage);
+  e = dev_alloc(&S.table, tbytes);
+  if (e != hipSuccess) return hip_fail(e, "Legendre table allocation");
+  e = hipMemsetAsync(S.table, 0, tbytes, st);
+  if (e != hipSuccess) return hip_fail(e, "table clear");
+  e = launch_table(g, S.x, S.s, S.row_off, S.rows_pad, storage, S.table, S.plane_stride, st);
+  if (e != hipSuccess) return hip_fail(e, "table kernel");
+
+  // workspace W[m][p][k][col]; padding rows / columns stay zero forever
+  const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.kpad * g.npad * sizeof(float);
+  e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
+  if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+  e = hipMemsetAsync(S.work, 0, wbytes, st);
+  if (e != hipSuccess) return hip_fail(e, "workspace clear");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "plan build");
+  return SHT_OK;
+}
+
+LegArgs leg_args(const Segment& S, bool analysis) {
+  LegArgs a{};
+  a.g = S.g;
+  a.table = S.table;
+  a.plane_stride = S.plane_stride;
+  a.row_off = S.row_off;
+  a.rows_pad = S.rows_pad;
+  a.tiles = analysis ? S.tiles_ana : S.tiles_syn;
+  a.ntiles = analysis ? S.n_ana : S.n_syn;
+  return a;
+}
+
+hipStream_t pick_stream(const sht_plan_s* p, void* s) {
+  return s ? static_cast<hipStream_t>(s) : p->stream;
+}
+
+enum Kind { K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5 };
+
+hipEvent_t take_event(sht_plan_s* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch `fn` (returning hipError_t) bracketed by timing events when enabled.
+template <typename Fn>
+hipError_t timed(sht_plan_s* p, int kind, hipStream_t st, Fn&& fn) {
+  if (!p->timing) return fn();
+  hipEvent_t a = take_event(p), b = take_event(p);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e == hipSuccess) {
+    p->pending.push_back(TimedLaunch{kind, a, b});
+  } else {
+    p->event_pool.push_back(a);
+    p->event_pool.push_back(b);
+  }
+  return e;
+}
+
+enum class Op { SHT, ISHT, SHT_T, ISHT_T };
+
+sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream) {
+  if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
+  if (!in || !out) return fail(SHT_ERR_INVALID_ARG, "input or output pointer is NULL");
+  if (in == out) return fail(SHT_ERR_INVALID_ARG, "input and output must not alias");
+  hipStream_t st = pick_stream(plan, stream);
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != plan->device) {
+    e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  sht_status rc = SHT_OK;
+  for (Segment& S : plan->segs) {
+    const SegGeom& g = S.g;
+    switch (op) {
+      case Op::SHT:
+      case Op::ISHT_T: {
+        const float* x = static_cast<const float*>(in) + S.grid_off;
+        float2* y = static_cast<float2*>(out) + S.spec_off;
+        const bool fwd = (op == Op::SHT);
+        e = timed(plan, K_DFT_FWD, st, [&] {
+          return launch_dft_forward(g, S.dp, x, S.work, S.tw, fwd ? S.scale_sht : S.scale_one, st);
+        });
+        if (e == hipSuccess)
+          e = timed(plan, K_LEG_ANA, st, [&] {
+            return launch_legendre_analysis(leg_args(S, true), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
+          });
+        if (e == hipSuccess) e = timed(plan, K_ZERO, st, [&] { return launch_zero_upper(g, y, st); });
+        break;
+      }
+      case Op::ISHT:
+      case Op::SHT_T: {
+        const float2* y = static_cast<const float2*>(in) + S.spec_off;
+        float* x = static_cast<float*>(out) + S.grid_off;
+        const bool inv = (op == Op::ISHT);
+        e = timed(plan, K_LEG_SYN, st, [&] {
+          return launch_legendre_synthesis(leg_args(S, false), plan->storage, y, S.work, st);
+        });
+        if (e == hipSuccess)
+          e = timed(plan, K_DFT_INV, st, [&] {
+            return launch_dft_inverse(g, S.dp, S.work, x, S.tw, inv ? S.scale_one : S.scale_sht, inv ? 2.f : 1.f,
+                                      st);
+          });
+        break;
+      }
+    }
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "kernel launch");
+      break;
+    }
+  }
+  if (cur != plan->device && cur >= 0) (void)hipSetDevice(cur);
+  return rc;
+}
+
+}  // namespace
+}  // namespace sht
+
+using namespace sht;
+
+extern "C" {
+
+sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_precision prec, void* hip_stream) {
+  if (!out) return fail(SHT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!descs) return fail(SHT_ERR_INVALID_ARG, "descs is NULL");
+  if (ndesc < 1 || ndesc > 64) return fail(SHT_ERR_INVALID_ARG, "ndesc must be in [1, 64]");
+  if (prec != SHT_PREC_FP32 && prec != SHT_PREC_BF16 && prec != SHT_PREC_BF16X2 && prec != SHT_PREC_BF16X3)
+    return fail(SHT_ERR_INVALID_ARG, "unknown precision %d", static_cast<int>(prec));
+  for (int i = 0; i < ndesc; ++i) {
+    sht_status s = validate_desc(descs[i], i);
+    if (s != SHT_OK) return s;
+  }
+  if (prec != SHT_PREC_FP32) return fail(SHT_ERR_UNSUPPORTED, "precision %d not built yet", static_cast<int>(prec));
+  // --- first HIP call below this line ---
+  auto* p = new (std::nothrow) sht_plan_s();
+  if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
+  p->prec = prec;
+  p->storage = storage_of(prec);
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  p->segs.resize(ndesc);
+  size_t goff = 0, soff = 0;
+  for (int i = 0; i < ndesc; ++i) {
+    Segment& S = p->segs[i];
+    S.grid_off = goff;
+    S.spec_off = soff;
+    const size_t F = static_cast<size_t>(descs[i].batch) * descs[i].channels;
+    goff += F * descs[i].nlat * descs[i].nlon;
+    soff += F * descs[i].lmax * descs[i].mmax;
+    sht_status rc = build_segment(S, descs[i], p->storage, p->stream);
+    if (rc != SHT_OK) {
+      for (Segment& T : p->segs) free_segment(T);
+      delete p;
+      return rc;
+    }
+  }
+  p->grid_elems = goff;
+  p->spec_elems = soff;
+  *out = p;
+  return SHT_OK;
+}
+
+sht_status sht_plan_destroy(sht_plan_t plan) {
+  if (!plan) return SHT_OK;
+  sht_status rc = SHT_OK;
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+  for (Segment& S : plan->segs) free_segment(S);
+  for (const TimedLaunch& t : plan->pending) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (hipEvent_t e : plan->event_pool) (void)hipEventDestroy(e);
+  delete plan;
+  return rc;
+}
+
+sht_status sht_plan_segment(sht_plan_t plan, int i, size_t* grid_offset, size_t* spec_offset) {
+  if (!plan || !grid_offset || !spec_offset) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (i < 0 || i >= static_cast<int>(plan->segs.size())) return fail(SHT_ERR_INVALID_ARG, "segment out of range");
+  *grid_offset = plan->segs[i].grid_off;
+  *spec_offset = plan->segs[i].spec_off;
+  return SHT_OK;
+}
+
+sht_status sht_plan_sizes(sht_plan_t plan, size_t* grid_elems, size_t* spec_elems) {
+  if (!plan || !grid_elems || !spec_elems) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  *grid_elems = plan->grid_elems;
+  *spec_elems = plan->spec_elems;
+  return SHT_OK;
+}
+
+sht_status sht_plan_grid(sht_plan_t plan, int i, double* x_host, double* w_host) {
+  if (!plan || !x_host || !w_host) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (i < 0 || i >= static_cast<int>(plan->segs.size())) return fail(SHT_ERR_INVALID_ARG, "segment out of range");
+  const Segment& S = plan->segs[i];
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e == hipSuccess) e = hipMemcpy(x_host, S.x, sizeof(double) * S.g.nlat, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(w_host, S.w, sizeof(double) * S.g.nlat, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "grid copy");
+  return SHT_OK;
+}
+
+sht_status sht_forward(sht_plan_t plan, const float* x, void* y, void* hip_stream) {
+  return run(plan, Op::SHT, x, y, hip_stream);
+}
+sht_status isht_forward(sht_plan_t plan, const void* y, float* x, void* hip_stream) {
+  return run(plan, Op::ISHT, y, x, hip_stream);
+}
+sht_status sht_backward(sht_plan_t plan, const void* gy, float* gx, void* hip_stream) {
+  return run(plan, Op::SHT_T, gy, gx, hip_stream);
+}
+sht_status isht_backward(sht_plan_t plan, const float* gx, void* gy, void* hip_stream) {
+  return run(plan, Op::ISHT_T, gx, gy, hip_stream);
+}
+
+sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void* out, int adjoint,
+                           void* hip_stream) {
+  if (!plan || !W || !in || !out) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (in == out) return fail(SHT_ERR_INVALID_ARG, "input and output must not alias");
+  if (plan->segs.size() != 1) return fail(SHT_ERR_INVALID_ARG, "channel mix needs a single-segment plan");
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_MIX, st, [&] {
+    return launch_channel_mix(d.batch, d.channels, d.lmax, d.mmax, static_cast<const float2*>(W),
+                              static_cast<const float2*>(in), static_cast<float2*>(out), adjoint, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "channel mix launch");
+  return SHT_OK;
+}
+
+sht_status sht_plan_timing(sht_plan_t plan, int enable) {
+  if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
+  plan->timing = enable != 0;
+  return SHT_OK;
+}
+
+sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds) {
+  if (!plan || !ms || !counts) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (nkinds < 1 || nkinds > SHT_TIMING_KINDS) return fail(SHT_ERR_INVALID_ARG, "nkinds out of range");
+  sht_status rc = SHT_OK;
+  for (const TimedLaunch& t : plan->pending) {
+    float el = 0.f;
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&el, t.start, t.stop);
+    if (e != hipSuccess && rc == SHT_OK) rc = hip_fail(e, "timing event");
+    if (e == hipSuccess && t.kind < nkinds) {
+      ms[t.kind] += el;
+      counts[t.kind] += 1;
+    }
+    plan->event_pool.push_back(t.start);
+    plan->event_pool.push_back(t.stop);
+  }
+  plan->pending.clear();
+  return rc;
+}
+
+const char* sht_status_string(sht_status s) {
+  switch (s) {
+    case SHT_OK: return "SHT_OK";
+    case SHT_ERR_INVALID_ARG: return "SHT_ERR_INVALID_ARG";
+    case SHT_ERR_UNSUPPORTED: return "SHT_ERR_UNSUPPORTED";
+    case SHT_ERR_OUT_OF_MEMORY: return "SHT_ERR_OUT_OF_MEMORY";
+    case SHT_ERR_HIP: return "SHT_ERR_HIP";
+    case SHT_ERR_INTERNAL: return "SHT_ERR_INTERNAL";
+  }
+  return "unknown sht_status";
+}
+
+const char* sht_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host plan code and the kernel files of
+// libsht.so.  Not part of the public ABI (include/sht.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace sht {
+
+// Rows of the folded Legendre table are padded per (m, parity) to a multiple
+// of this, so that every row tile of the contraction kernels is full.
+constexpr int kRowPad = 64;
+// Ring (contraction K) dimension of the table and workspace is padded to a
+// multiple of this.
+constexpr int kRingPad = 32;
+// Column (field) dimension of the workspace is padded to a multiple of this.
+constexpr int kColPad = 64;
+// Longest ring DFT supported (LDS budget of the DFT kernels).
+constexpr int kMaxNlon = 4096;
+constexpr int kMaxRadices = 16;
+
+// Storage of the Legendre table / data operands of the contraction.
+enum class Storage : int { F32 = 0, BF16 = 1, BF16X2 = 2, BF16X3 = 3 };
+
+// Geometry of one segment as the kernels see it.
+struct SegGeom {
+  int nlat, nlon, lmax, mmax;
+  int F;          // fields = batch * channels
+  int nk;         // northern rings incl. the equator: (nlat + 1) / 2
+  int kpad;       // nk rounded up to kRingPad
+  int npad;       // 2F rounded up to kColPad (workspace row length, floats)
+  bool has_equator;  // nlat odd
+};
+
+// ---- grid_table.hip ----------------------------------------------------
+// Nodes x_k, sin t_k and latitude weights w_k (float64, nlat each).
+hipError_t launch_grid(int nlat, int kind, double* x, double* s, double* w, hipStream_t st);
+// Folded float64 recurrence for P^_l^m(x_k), k < nk, written in storage form.
+// row_off[m]: first row of order m; rows_pad[m]: rows per parity block.
+// planes: number of bf16 planes (1 for BF16, 2 for BF16X2, 3 for BF16X3);
+// for F32 `table` holds floats.  Plane stride (elements) = plane_stride.
+hipError_t launch_table(const SegGeom& g, const double* x, const double* s, const int64_t* row_off,
+                        const int* rows_pad, Storage st, void* table, size_t plane_stride,
+                        hipStream_t stream);
+
+// ---- dft.hip -------------------------------------------------------------
+struct DftPlan {
+  int n;                       // nlon
+  int nstages;
+  int radix[kMaxRadices];
+};
+bool make_dft_plan(int n, DftPlan* p);
+
+// Forward ring DFT of the ring pairs (k, nlat-1-k), k < nk, multiplied by
+// ring_scale[k], folded into symmetric/antisymmetric parts and written to
+// the workspace W[m][p][k][col] (float32 complex pairs at col = 2f, 2f+1).
+hipError_t launch_dft_forward(const SegGeom& g, const DftPlan& dp, const float* x, float* W,
+                              const float2* tw, const float* ring_scale, hipStream_t st);
+// Inverse: reads E = W[m][0], O = W[m][1], north = E + O, south = E - O,
+// synthesises sum_m c_m Re(Y e^{i m p}) with c_0 = 1, c_m = c_rest, scales
+// ring k by ring_scale[k] and writes the grid tensor.
+hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* W, float* x,
+                              const float2* tw, const float* ring_scale, float c_rest,
+                              hipStream_t st);
+
+// ---- legendre.hip --------------------------------------------------------
+// Tile lists: int4 {m, parity, row0, 0} for analysis (row tiles of the
+// parity block) and {m, parity, k0, 0} for synthesis (ring tiles).
+struct LegArgs {
+  SegGeom g;
+  const void* table;
+  size_t plane_stride;
+  const int64_t* row_off;
+  const int* rows_pad;
+  const int4* tiles;
+  int ntiles;
+};
+// y[f][l][m] = mscale_m * sum_k P[m][p][i][k] W[m][p][k][2f..]   (l = m + p + 2i)
+hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y,
+                                    float c_rest, hipStream_t stream);
+// W[m][p][k][2f..] = sum_i P[m][p][i][k] y[f][m + p + 2i][m]
+hipError_t launch_legendre_synthesis(const LegArgs& a, Storage st, const float2* y, float* W,
+                                     hipStream_t stream);
+// y[f][l][m] = 0 for l < m.
+hipError_t launch_zero_upper(const SegGeom& g, float2* y, hipStream_t stream);
+
+// ---- mix.hip -------------------------------------------------------------
+hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
+                              const float2* in, float2* out, int adjoint, hipStream_t stream);
+
+}  // namespace sht

@@ -1,0 +1,113 @@
+// Per-degree complex channel mix: out[b,c',l,m] = sum_c W[l,c',c] in[b,c,l,m]
+// (adjoint: conj(W[l,c,c'])), the multi-channel per-degree filter of the
+// spectral convolution (App. B.4, eq. s2_spectral_conv: the filter depends on
+// l only, never on m).
+//
+// For each degree l this is a complex GEMM  W_l (C x C) @ X_l (C x B*(l+1)),
+// columns (b, m) with m <= min(l, mmax-1).  A workgroup computes a 32 x 32
+// output tile through 16-deep LDS-staged slices; each thread owns a 2 x 2
+// block of complex outputs.
+#include "internal.h"
+
+namespace sht {
+namespace {
+
+constexpr int MT = 32, NT = 32, KT = 16;
+
+__global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax, int mmax,
+                                                          const float2* __restrict__ W,
+                                                          const float2* __restrict__ in,
+                                                          float2* __restrict__ out, int adjoint) {
+  __shared__ float2 sW[KT][MT + 1];
+  __shared__ float2 sX[KT][NT + 1];
+  const int l = blockIdx.z;
+  const int mcount = (l + 1 < mmax) ? l + 1 : mmax;  // orders m <= l
+  const int ncols = B * mcount;
+  const int c0 = blockIdx.y * MT;   // output channel tile
+  const int j0 = blockIdx.x * NT;   // (b, m) column tile
+  if (j0 >= ncols) return;
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;  // 16 x 16 threads, 2 x 2 outputs each
+  float2 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  const size_t wl = static_cast<size_t>(l) * C * C;
+  for (int k0 = 0; k0 < C; k0 += KT) {
+    for (int e = tid; e < KT * MT; e += 256) {
+      const int kk = e / MT, i = e % MT;
+      const int co = c0 + i, ci = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (co < C && ci < C) {
+        if (adjoint) {
+          v = W[wl + static_cast<size_t>(ci) * C + co];
+          v.y = -v.y;
+        } else {
+          v = W[wl + static_cast<size_t>(co) * C + ci];
+        }
+      }
+      sW[kk][i] = v;
+    }
+    for (int e = tid; e < KT * NT; e += 256) {
+      const int kk = e / NT, j = e % NT;
+      const int col = j0 + j, ci = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (col < ncols && ci < C) {
+        const int b = col / mcount, m = col % mcount;
+        v = in[((static_cast<size_t>(b) * C + ci) * lmax + l) * mmax + m];
+      }
+      sX[kk][j] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < KT; ++kk) {
+      float2 wv[2], xv[2];
+      for (int i = 0; i < 2; ++i) wv[i] = sW[kk][tr + 16 * i];
+      for (int j = 0; j < 2; ++j) xv[j] = sX[kk][tc + 16 * j];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j].x += wv[i].x * xv[j].x - wv[i].y * xv[j].y;
+          acc[i][j].y += wv[i].x * xv[j].y + wv[i].y * xv[j].x;
+        }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int co = c0 + tr + 16 * i;
+      const int col = j0 + tc + 16 * j;
+      if (co < C && col < ncols) {
+        const int b = col / mcount, m = col % mcount;
+        out[((static_cast<size_t>(b) * C + co) * lmax + l) * mmax + m] = acc[i][j];
+      }
+    }
+}
+
+// out[b, c, l, m] = 0 for m > l (the part the mix kernel never writes).
+__global__ void mix_zero_kernel(int B, int C, int lmax, int mmax, float2* __restrict__ out) {
+  const size_t total = static_cast<size_t>(B) * C * lmax * mmax;
+  for (size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int m = static_cast<int>(idx % mmax);
+    const int l = static_cast<int>((idx / mmax) % lmax);
+    if (m > l) out[idx] = make_float2(0.f, 0.f);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
+                              const float2* in, float2* out, int adjoint, hipStream_t stream) {
+  const int maxcols = batch * mmax;
+  dim3 grid((maxcols + NT - 1) / NT, (channels + MT - 1) / MT, lmax);
+  hipLaunchKernelGGL(channel_mix_kernel, grid, dim3(256), 0, stream, batch, channels, lmax, mmax, W, in,
+                     out, adjoint);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t total = static_cast<size_t>(batch) * channels * lmax * mmax;
+  size_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(mix_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch,
+                     channels, lmax, mmax, out);
+  return hipGetLastError();
+}
+
+}  // namespace sht

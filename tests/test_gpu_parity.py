@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Each case prints its name before running so that a failing GPU step can be
+identified from the log.  Tolerance for float32 (and split-bf16) results is
+the relative L2 bound 1e-5 of the FP64 oracle (over the whole output, complex
+entries counted as two reals), evaluated on the oracle applied to the same
+float32-rounded input.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _util import ensure_built, per_degree_errors, rel_l2
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    ensure_built()
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_12144_amd as P
+    return P
+
+
+def _plan(P, nlat, nlon, lmax, mmax, grid, batch, channels, precision="fp32"):
+    return P.Plan(dict(nlat=nlat, nlon=nlon, lmax=lmax, mmax=mmax, grid=grid, batch=batch, channels=channels),
+                  precision=precision)
+
+
+def _to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def _four_transforms(P, plan, shape, seed, prec_tol=TOL):
+    """Run SHT, ISHT, SHT^T, ISHT^T on seeded inputs; return the four rel-L2s."""
+    nlat, nlon, lmax, mmax, grid, B, C = shape
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((B, C, nlat, nlon)).astype(np.float32)
+    a = synth.coefficients(seed + 1, B, C, lmax, mmax).astype(np.complex64)
+    u64 = u.astype(np.float64)
+    a64 = a.astype(np.complex128)
+    du = _to_dev(u, torch.float32)
+    da = _to_dev(a, torch.complex64)
+    y = plan.sht(du).cpu().numpy()
+    x = plan.isht(da).cpu().numpy()
+    gx = plan.sht_T(da).cpu().numpy()
+    gy = plan.isht_T(du).cpu().numpy()
+    torch.cuda.synchronize()
+    ref_y = oracle.sht(u64, lmax, mmax, grid)
+    ref_x = oracle.isht(a64, nlat, nlon, grid)
+    ref_gx = oracle.sht_T(a64, nlat, nlon, grid)
+    ref_gy = oracle.isht_T(u64, lmax, mmax, grid)
+    errs = (rel_l2(y, ref_y), rel_l2(x, ref_x), rel_l2(gx, ref_gx), rel_l2(gy, ref_gy))
+    # exact structural zeros of the spectral outputs
+    l = np.arange(lmax)[:, None]
+    m = np.arange(mmax)[None, :]
+    for out in (y, gy):
+        assert np.all(out[..., l < m] == 0)
+        assert np.all(out[..., 0].imag == 0)
+    return errs
+
+
+SMALL = [
+    # nlat, nlon, lmax, mmax, grid, batch, channels
+    (32, 64, 32, 32, 1, 1, 4),       # the tiny Gauss-Legendre case
+    (33, 64, 17, 17, 0, 1, 3),       # odd equiangular, equator ring, band limit
+    (65, 128, 64, 40, 0, 2, 3),      # mmax < lmax
+    (48, 96, 48, 48, 1, 1, 37),      # 74 columns: ragged second column tile
+    (45, 90, 40, 40, 2, 1, 2),       # trapezoid weights, nlon = 2 * 3^2 * 5
+    (181, 360, 180, 180, 0, 1, 5),   # 0.5 degree grid shape
+    (16, 30, 10, 10, 1, 3, 1),       # nlon = 2 * 3 * 5
+    (2, 2, 1, 1, 1, 1, 1),           # smallest legal transform
+    (3, 4, 2, 2, 0, 1, 1),           # equator only besides the poles
+    (9, 16, 30, 8, 1, 1, 2),         # lmax > nlat (aliased but well defined)
+    (64, 128, 130, 64, 0, 1, 65),    # 130 columns, many row tiles per m
+]
+
+
+@pytest.mark.parametrize("shape", SMALL, ids=[f"{s[0]}x{s[1]}_L{s[2]}M{s[3]}_g{s[4]}_F{s[5]*s[6]}" for s in SMALL])
+def test_small_parity_fp32(pkg, shape):
+    _say("case", shape)
+    plan = _plan(pkg, *shape)
+    errs = _four_transforms(pkg, plan, shape, seed=3)
+    _say("  rel-L2 sht/isht/sht_T/isht_T:", errs)
+    assert max(errs) <= TOL, errs
+    plan.close()
+
+
+@pytest.mark.parametrize("nlat,grid", [(32, 1), (360, 1), (721, 0), (181, 0), (65, 2), (2, 1), (3, 0)])
+def test_grid_matches_oracle(pkg, nlat, grid):
+    _say("grid", nlat, grid)
+    plan = _plan(pkg, nlat, 64, 2, 1, grid, 1, 1)
+    x, w = plan.grid()
+    _, xr, wr = oracle.grid(nlat, grid)
+    np.testing.assert_allclose(x.numpy(), xr, atol=4e-16)
+    np.testing.assert_allclose(w.numpy(), wr, rtol=1e-11, atol=1e-17)
+    plan.close()
+
+
+def test_full_size_equiangular_721_fp32(pkg):
+    """721 x 1440, lmax = mmax = 720, 72 fields: the benchmark workload.
+    Input: band-limited field (seed 0) plus a 1e-3 white-noise probe
+    (seed 1), cast to float32; every output compared element by element."""
+    nlat, nlon, L, B, C = 721, 1440, 720, 1, 72
+    _say("full size 721x1440 fp32: building inputs")
+    a = synth.coefficients(0, B, C, L, L)
+    u = oracle.isht(a, nlat, nlon, 0) + synth.white_noise(1, (B, C, nlat, nlon))
+    u32 = u.astype(np.float32)
+    plan = _plan(pkg, nlat, nlon, L, L, 0, B, C)
+    du = _to_dev(u32, torch.float32)
+    y = plan.sht(du)
+    x = plan.isht(y)
+    gy = plan.isht_T(x)
+    gx = plan.sht_T(gy)
+    y, x, gy, gx = (t.cpu().numpy() for t in (y, x, gy, gx))
+    _say("  oracle")
+    # each stage's reference from the GPU stage's own (float32) input
+    ref_y = oracle.sht(u32.astype(np.float64), L, L, 0)
+    e1 = rel_l2(y, ref_y)
+    rel, mx = per_degree_errors(y, ref_y)
+    _say(f"  sht rel-L2 {e1:.3e}; worst degree rel-L2 {rel.max():.3e} at l={int(rel.argmax())}")
+    ref_x = oracle.isht(y.astype(np.complex128), nlat, nlon, 0)
+    e2 = rel_l2(x, ref_x)
+    ref_gy = oracle.isht_T(x.astype(np.float64), L, L, 0)
+    e3 = rel_l2(gy, ref_gy)
+    ref_gx = oracle.sht_T(gy.astype(np.complex128), nlat, nlon, 0)
+    e4 = rel_l2(gx, ref_gx)
+    _say(f"  rel-L2 sht {e1:.3e} isht {e2:.3e} isht_T {e3:.3e} sht_T {e4:.3e}")
+    assert max(e1, e2, e3, e4) <= TOL
+    plan.close()
+
+
+def _rdot(a, b):
+    return float(np.sum(np.real(np.conj(a.astype(np.complex128)) * b.astype(np.complex128))))
+
+
+@pytest.mark.parametrize("shape", [(33, 64, 17, 17, 0, 1, 3), (48, 96, 48, 48, 1, 2, 5), (181, 360, 180, 180, 0, 1, 8)])
+def test_gpu_adjoint_dot_products(pkg, shape):
+    _say("dot", shape)
+    nlat, nlon, lmax, mmax, grid, B, C = shape
+    plan = _plan(pkg, *shape)
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((B, C, nlat, nlon)).astype(np.float32)
+    g = synth.coefficients(22, B, C, lmax, mmax).astype(np.complex64)
+    du, dg = _to_dev(u, torch.float32), _to_dev(g, torch.complex64)
+    lhs = _rdot(plan.sht(du).cpu().numpy(), g)
+    rhs = _rdot(u, plan.sht_T(dg).cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs) + 1e-30) + 1e-6
+    lhs = _rdot(plan.isht(dg).cpu().numpy(), u)
+    rhs = _rdot(g, plan.isht_T(du).cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs) + 1e-30) + 1e-6
+    plan.close()
+
+
+def test_autograd_functions(pkg):
+    _say("autograd")
+    P = pkg
+    shape = (32, 64, 32, 32, 1, 2, 3)
+    nlat, nlon, lmax, mmax, grid, B, C = shape
+    plan = _plan(P, *shape)
+    rng = np.random.default_rng(5)
+    u = _to_dev(rng.standard_normal((B, C, nlat, nlon)), torch.float32).requires_grad_(True)
+    r = rng.standard_normal((B, C, nlat, nlon))
+    W = synth.mix_weights(4, lmax, C)
+    loss = (P.ISHT.apply(P.ChannelMix.apply(P.SHT.apply(u, plan), _to_dev(W, torch.complex64), plan), plan)
+            * _to_dev(r, torch.float32)).sum()
+    loss.backward()
+    ref = oracle.sht_T(oracle.channel_mix_T(oracle.isht_T(r, lmax, mmax, grid), W), nlat, nlon, grid)
+    err = rel_l2(u.grad.cpu().numpy(), ref)
+    _say("  grad rel-L2", err)
+    assert err <= TOL
+    plan.close()
+
+
+def test_channel_mix_parity(pkg):
+    _say("mix")
+    shape = (24, 48, 24, 20, 1, 2, 37)
+    nlat, nlon, lmax, mmax, grid, B, C = shape
+    plan = _plan(pkg, *shape)
+    x = synth.coefficients(8, B, C, lmax, mmax)
+    W = synth.mix_weights(9, lmax, C)
+    dx, dW = _to_dev(x, torch.complex64), _to_dev(W, torch.complex64)
+    y = plan.mix(dW, dx).cpu().numpy()
+    yT = plan.mix(dW, dx, adjoint=True).cpu().numpy()
+    assert rel_l2(y, oracle.channel_mix(x, W)) <= TOL
+    assert rel_l2(yT, oracle.channel_mix_T(x, W)) <= TOL
+    l = np.arange(lmax)[:, None]
+    m = np.arange(mmax)[None, :]
+    assert np.all(y[..., l < m] == 0)
+    plan.close()
+
+
+def test_bitwise_determinism(pkg):
+    _say("determinism")
+    shape = (181, 360, 180, 180, 0, 1, 9)
+    plan = _plan(pkg, *shape)
+    rng = np.random.default_rng(2)
+    du = _to_dev(rng.standard_normal((1, 9, 181, 360)), torch.float32)
+    y1 = plan.sht(du).clone()
+    x1 = plan.isht(y1).clone()
+    y2 = plan.sht(du)
+    x2 = plan.isht(y2)
+    assert torch.equal(y1, y2) and torch.equal(x1, x2)
+    plan.close()
+
+
+def test_python_argument_checks(pkg):
+    plan = _plan(pkg, 16, 32, 16, 16, 1, 1, 2)
+    with pytest.raises(ValueError):
+        plan.sht(torch.zeros(1, 2, 16, 32, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.sht(torch.zeros(1, 2, 16, 31, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.isht(torch.zeros(1, 2, 16, 16, dtype=torch.complex64, device="cuda").transpose(-1, -2))
+    with pytest.raises(ValueError):
+        plan.sht(torch.zeros(1, 2, 16, 32))
+    plan.close()
+
+
+def test_non_default_stream(pkg):
+    _say("stream")
+    shape = (33, 64, 17, 17, 0, 1, 3)
+    plan = _plan(pkg, *shape)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((1, 3, 33, 64)).astype(np.float32)
+    du = _to_dev(u, torch.float32)
+    ref = plan.sht(du).clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        y = plan.sht(du)
+    torch.cuda.current_stream().wait_stream(s)
+    assert torch.equal(y, ref)
+    plan.close()
