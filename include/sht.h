@@ -27,8 +27,9 @@
  *    fields: u^_l^{-m} = (-1)^m conj(u^_l^m)).
  *  - All tensors are DEVICE pointers owned by the caller.  In/out buffers
  *    must not alias.  With several descriptors (the batching form) each
- *    buffer is the concatenation of the segments in descriptor order; use
- *    sht_plan_segment for the element offsets.
+ *    buffer is the concatenation of the segments in descriptor order, each
+ *    segment starting at a multiple of 64 elements; use sht_plan_segment for
+ *    the element offsets and sht_plan_sizes for the totals.
  *  - Calls enqueue work on hip_stream (NULL: the plan's own stream) and
  *    return without waiting.  A kernel fault surfaces as SHT_ERR_HIP on a
  *    later call or on the caller's synchronisation.  One stream at a time
@@ -51,8 +52,8 @@ extern "C" {
 typedef enum {
     SHT_OK = 0,
     SHT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, unknown enum        */
-    SHT_ERR_UNSUPPORTED = 2,   /* valid but not implemented (e.g. a prime
-                                  factor > 5 in nlon, nlon > 4096)          */
+    SHT_ERR_UNSUPPORTED = 2,   /* valid but not implemented: a prime factor
+                                  > 5 in nlon, nlon > 2048, nlat > 768       */
     SHT_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed                 */
     SHT_ERR_HIP = 4,           /* a HIP runtime call failed                  */
     SHT_ERR_INTERNAL = 5

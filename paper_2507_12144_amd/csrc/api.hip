@@ -3,6 +3,7 @@
 // in include/sht.h.  Every argument check runs before the first HIP call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <cstdarg>
@@ -95,10 +96,11 @@ struct Segment {
   int* rows_pad = nullptr;
   void* table = nullptr;
   size_t plane_stride = 0;
-  int4* tiles_ana = nullptr;
-  int n_ana = 0;
-  int4* tiles_syn = nullptr;
-  int n_syn = 0;
+  int2* worklist = nullptr;
+  int work_per = 0;
+  int2* worklist_syn = nullptr;
+  int work_syn_per = 0;
+  int ncb = 1;
   float* work = nullptr;
 };
 
@@ -115,6 +117,8 @@ sht_status validate_desc(const sht_desc& d, int i) {
   if (d.grid != SHT_GRID_EQUIANGULAR && d.grid != SHT_GRID_GAUSS && d.grid != SHT_GRID_EQUIANGULAR_TRAPEZOID)
     return fail(SHT_ERR_INVALID_ARG, "desc %d: unknown grid %d", i, static_cast<int>(d.grid));
   if (d.nlon > kMaxNlon) return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlon > %d", i, kMaxNlon);
+  if ((d.nlat + 1) / 2 > kMaxRings)
+    return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlat > %d", i, 2 * kMaxRings);
   if (!only_small_primes(d.nlon))
     return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlon = %d has a prime factor > 5", i, d.nlon);
   const long long F = static_cast<long long>(d.batch) * d.channels;
@@ -148,7 +152,7 @@ namespace {
 
 void free_segment(Segment& s) {
   void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.row_off, s.rows_pad, s.table,
-                  s.tiles_ana, s.tiles_syn, s.work};
+                  s.worklist, s.worklist_syn, s.work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = Segment{};
@@ -181,8 +185,10 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   g.F = d.batch * d.channels;
   g.nk = (d.nlat + 1) / 2;
   g.has_equator = (d.nlat % 2) == 1;
-  g.kpad = static_cast<int>(round_up(g.nk, kRingPad));
-  g.npad = static_cast<int>(round_up(2 * static_cast<size_t>(g.F), kColPad));
+  g.kpad = legendre_ring_pad(g.nk);
+  g.groups = (g.F + 7) / 8;
+  if (g.kpad < 0) return fail(SHT_ERR_UNSUPPORTED, "nlat = %d: more than %d northern rings", d.nlat, kMaxRings);
+  S.ncb = legendre_ncb(g.groups);
   if (!make_dft_plan(d.nlon, &S.dp)) return fail(SHT_ERR_UNSUPPORTED, "nlon = %d cannot be factored", d.nlon);
 
   hipError_t e;
@@ -214,26 +220,40 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   std::vector<int64_t> row_off(d.mmax);
   std::vector<int> rows_pad(d.mmax);
   int64_t rows = 0;
-  std::vector<int4> ana, syn;
   for (int m = 0; m < d.mmax; ++m) {
     const int n0 = (d.lmax - m + 1) / 2;
-    const int n1 = (d.lmax - m) / 2;
     rows_pad[m] = static_cast<int>(round_up(n0 > 0 ? n0 : 1, kRowPad));
     row_off[m] = rows;
     rows += 2LL * rows_pad[m];
-    for (int p = 0; p < 2; ++p) {
-      const int np = p == 0 ? n0 : n1;
-      for (int r = 0; r < np; r += 64) ana.push_back(make_int4(m, p, r, 0));
-      if (np > 0)
-        for (int k = 0; k < g.kpad; k += 64) syn.push_back(make_int4(m, p, k, 0));
-    }
   }
   if ((rc = upload(&S.row_off, row_off, st, "table offsets")) != SHT_OK) return rc;
   if ((rc = upload(&S.rows_pad, rows_pad, st, "table offsets")) != SHT_OK) return rc;
-  if ((rc = upload(&S.tiles_ana, ana, st, "tile list")) != SHT_OK) return rc;
-  if ((rc = upload(&S.tiles_syn, syn, st, "tile list")) != SHT_OK) return rc;
-  S.n_ana = static_cast<int>(ana.size());
-  S.n_syn = static_cast<int>(syn.size());
+
+  // contraction work list: chunks of 16 consecutive m dealt round-robin to
+  // the 8 XCDs, each XCD's chunks in ascending m (largest work first)
+  for (int syn = 0; syn < 2; ++syn) {
+    const int chunks_per_m = (g.groups + S.ncb - 1) / S.ncb;
+    const int sub = syn ? 2 : 1;  // the synthesis splits the rings in two halves
+    std::vector<std::vector<int2>> slices(8);
+    for (int q = 0; q * 16 < d.mmax; ++q)
+      for (int m = 16 * q; m < std::min(d.mmax, 16 * q + 16); ++m)
+        for (int c = 0; c < chunks_per_m * sub; ++c) slices[q % 8].push_back(make_int2(m, c));
+    size_t per = 1;
+    for (auto& v : slices) per = std::max(per, v.size());
+    std::vector<int2> flat;
+    flat.reserve(8 * per);
+    for (auto& v : slices) {
+      v.resize(per, make_int2(-1, -1));
+      flat.insert(flat.end(), v.begin(), v.end());
+    }
+    if (syn) {
+      S.work_syn_per = static_cast<int>(per);
+      if ((rc = upload(&S.worklist_syn, flat, st, "work list")) != SHT_OK) return rc;
+    } else {
+      S.work_per = static_cast<int>(per);
+      if ((rc = upload(&S.worklist, flat, st, "work list")) != SHT_OK) return rc;
+    }
+  }
 
   const size_t entries = static_cast<size_t>(rows) * g.kpad;
   S.plane_stride = entries;
@@ -245,8 +265,8 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   e = launch_table(g, S.x, S.s, S.row_off, S.rows_pad, storage, S.table, S.plane_stride, st);
   if (e != hipSuccess) return hip_fail(e, "table kernel");
 
-  // workspace W[m][p][k][col]; padding rows / columns stay zero forever
-  const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.kpad * g.npad * sizeof(float);
+  // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
+  const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.groups * g.kpad * 16 * sizeof(float);
   e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
   if (e != hipSuccess) return hip_fail(e, "workspace allocation");
   e = hipMemsetAsync(S.work, 0, wbytes, st);
@@ -256,15 +276,18 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   return SHT_OK;
 }
 
-LegArgs leg_args(const Segment& S, bool analysis) {
+LegArgs leg_args(const Segment& S) {
   LegArgs a{};
   a.g = S.g;
   a.table = S.table;
   a.plane_stride = S.plane_stride;
   a.row_off = S.row_off;
   a.rows_pad = S.rows_pad;
-  a.tiles = analysis ? S.tiles_ana : S.tiles_syn;
-  a.ntiles = analysis ? S.n_ana : S.n_syn;
+  a.work = S.worklist;
+  a.work_per = S.work_per;
+  a.work_syn = S.worklist_syn;
+  a.work_syn_per = S.work_syn_per;
+  a.ncb = S.ncb;
   return a;
 }
 
@@ -331,9 +354,8 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
         });
         if (e == hipSuccess)
           e = timed(plan, K_LEG_ANA, st, [&] {
-            return launch_legendre_analysis(leg_args(S, true), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
+            return launch_legendre_analysis(leg_args(S), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
           });
-        if (e == hipSuccess) e = timed(plan, K_ZERO, st, [&] { return launch_zero_upper(g, y, st); });
         break;
       }
       case Op::ISHT:
@@ -342,7 +364,7 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
         float* x = static_cast<float*>(out) + S.grid_off;
         const bool inv = (op == Op::ISHT);
         e = timed(plan, K_LEG_SYN, st, [&] {
-          return launch_legendre_synthesis(leg_args(S, false), plan->storage, y, S.work, st);
+          return launch_legendre_synthesis(leg_args(S), plan->storage, y, S.work, st);
         });
         if (e == hipSuccess)
           e = timed(plan, K_DFT_INV, st, [&] {
@@ -398,8 +420,9 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
     S.grid_off = goff;
     S.spec_off = soff;
     const size_t F = static_cast<size_t>(descs[i].batch) * descs[i].channels;
-    goff += F * descs[i].nlat * descs[i].nlon;
-    soff += F * descs[i].lmax * descs[i].mmax;
+    // segments start on 64-element boundaries (256-byte aligned grid data)
+    goff = round_up(goff + F * descs[i].nlat * descs[i].nlon, 64);
+    soff = round_up(soff + F * descs[i].lmax * descs[i].mmax, 64);
     sht_status rc = build_segment(S, descs[i], p->storage, p->stream);
     if (rc != SHT_OK) {
       for (Segment& T : p->segs) free_segment(T);

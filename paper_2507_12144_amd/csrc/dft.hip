@@ -2,24 +2,31 @@
 // along W, then keep m < mmax" of Alg. 1) and its inverse.
 //
 // Design (gfx950):
-//  * A workgroup owns one ring pair (k, nlat-1-k) for `fg` fields.  The two
+//  * A workgroup owns one ring pair (k, nlat-1-k) for 4 fields.  The two
 //    real rings of a field are packed as one complex sequence z = u_k + i u_k'
 //    (the mirrored ring), so one complex FFT of length nlon yields both real
 //    spectra, and the pair is exactly what the equatorial fold of the
 //    Legendre step needs: S = X_k + X_k' and A = X_k - X_k'.
-//  * The complex FFT is a mixed-radix (4, 2, 3, 5) Stockham autosort in LDS
-//    (ping-pong buffers, no bit reversal), each thread doing radix-R
-//    butterflies in registers with twiddles from a float32 table built in
-//    float64 on the host.
-//  * Grid rows are read / written as contiguous nlon-float runs; the
-//    workspace is written / read as fg*8-byte runs per (m, parity, ring).
+//  * The complex FFT is a Stockham autosort in LDS.  For the grid widths of
+//    the 0.25/0.5/1 degree and small test grids (1440, 720, 360, 64) it runs
+//    three (two) in-place passes of radix 9/10/16-type butterflies, each a
+//    composite DFT held in registers; other widths 2^a 3^b 5^c take a
+//    runtime-radix (2, 3, 4, 5) ping-pong path.
+//  * Workspace layout W[m][p][g][k][16]: g = group of 8 fields, 16 floats =
+//    (re, im) of those fields.  A workgroup writes / reads 32-byte runs; the
+//    block order is remapped so that the workgroups completing one 128-byte
+//    line run together on the same XCD (which merges them in its L2).
 #include "internal.h"
 
 namespace sht {
 namespace {
 
+constexpr int FGW = 4;     // fields per workgroup
+constexpr int NT = 256;    // threads per workgroup
+
 struct DftArgs {
-  int nlat, nlon, lmax, mmax, nk, F, kpad, npad, fg;
+  int nlat, nlon, lmax, mmax, nk, F, kpad, G;
+  int nitems;              // G * nk * 2 workgroup items
   int nstages;
   int radix[kMaxRadices];
   float c_rest;
@@ -34,63 +41,227 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 // multiply by +i (sg = +1) or -i (sg = -1)
 __device__ __forceinline__ float2 mul_i(float2 a, float sg) { return make_float2(-sg * a.y, sg * a.x); }
 
+// cos / sin of 2 pi e / R for the composite radices (e < R).
+template <int R>
+__device__ __forceinline__ float root_cos(int e);
+template <int R>
+__device__ __forceinline__ float root_sin(int e);
+
+#define SHT_ROOTS(R, ...)                                                    \
+  template <>                                                                \
+  __device__ __forceinline__ float root_cos<R>(int e) {                      \
+    constexpr float c[R] = {__VA_ARGS__};                                    \
+    return c[e];                                                             \
+  }
+SHT_ROOTS(8, 1.f, 0.70710678118654752f, 0.f, -0.70710678118654752f, -1.f, -0.70710678118654752f, 0.f,
+          0.70710678118654752f)
+SHT_ROOTS(9, 1.f, 0.76604444311897804f, 0.17364817766693035f, -0.5f, -0.93969262078590838f,
+          -0.93969262078590838f, -0.5f, 0.17364817766693035f, 0.76604444311897804f)
+SHT_ROOTS(10, 1.f, 0.80901699437494742f, 0.30901699437494742f, -0.30901699437494742f, -0.80901699437494742f,
+          -1.f, -0.80901699437494742f, -0.30901699437494742f, 0.30901699437494742f, 0.80901699437494742f)
+SHT_ROOTS(16, 1.f, 0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f, 0.f,
+          -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128676f, -1.f, -0.92387953251128676f,
+          -0.70710678118654752f, -0.38268343236508977f, 0.f, 0.38268343236508977f, 0.70710678118654752f,
+          0.92387953251128676f)
+#undef SHT_ROOTS
+// sin(2 pi e / R) = cos(2 pi (e - R/4) / R) for R divisible by 4; listed
+// explicitly for the odd-quarter radices.
+template <>
+__device__ __forceinline__ float root_sin<8>(int e) {
+  constexpr float s[8] = {0.f, 0.70710678118654752f, 1.f, 0.70710678118654752f, 0.f, -0.70710678118654752f, -1.f,
+                          -0.70710678118654752f};
+  return s[e];
+}
+template <>
+__device__ __forceinline__ float root_sin<9>(int e) {
+  constexpr float s[9] = {0.f, 0.64278760968653933f, 0.98480775301220806f, 0.86602540378443865f,
+                          0.34202014332566873f, -0.34202014332566873f, -0.86602540378443865f,
+                          -0.98480775301220806f, -0.64278760968653933f};
+  return s[e];
+}
+template <>
+__device__ __forceinline__ float root_sin<10>(int e) {
+  constexpr float s[10] = {0.f, 0.58778525229247313f, 0.95105651629515357f, 0.95105651629515357f,
+                           0.58778525229247313f, 0.f, -0.58778525229247313f, -0.95105651629515357f,
+                           -0.95105651629515357f, -0.58778525229247313f};
+  return s[e];
+}
+template <>
+__device__ __forceinline__ float root_sin<16>(int e) {
+  constexpr float s[16] = {0.f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128676f, 1.f,
+                           0.92387953251128676f, 0.70710678118654752f, 0.38268343236508977f, 0.f,
+                           -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128676f, -1.f,
+                           -0.92387953251128676f, -0.70710678118654752f, -0.38268343236508977f};
+  return s[e];
+}
+
 // In-register DFT of length R: A_s = sum_q a_q e^{sg 2 pi i q s / R}.
 template <int R>
-__device__ __forceinline__ void codelet(float2* a, float sg);
+struct Codelet;
 
 template <>
-__device__ __forceinline__ void codelet<2>(float2* a, float) {
-  const float2 t = a[1];
-  a[1] = csub(a[0], t);
-  a[0] = cadd(a[0], t);
-}
+struct Codelet<2> {
+  __device__ static __forceinline__ void run(float2* a, float) {
+    const float2 t = a[1];
+    a[1] = csub(a[0], t);
+    a[0] = cadd(a[0], t);
+  }
+};
 
 template <>
-__device__ __forceinline__ void codelet<4>(float2* a, float sg) {
-  const float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
-  const float2 s13 = cadd(a[1], a[3]), d13 = mul_i(csub(a[1], a[3]), sg);
-  a[0] = cadd(s02, s13);
-  a[2] = csub(s02, s13);
-  a[1] = cadd(d02, d13);
-  a[3] = csub(d02, d13);
-}
+struct Codelet<4> {
+  __device__ static __forceinline__ void run(float2* a, float sg) {
+    const float2 s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    const float2 s13 = cadd(a[1], a[3]), d13 = mul_i(csub(a[1], a[3]), sg);
+    a[0] = cadd(s02, s13);
+    a[2] = csub(s02, s13);
+    a[1] = cadd(d02, d13);
+    a[3] = csub(d02, d13);
+  }
+};
 
 template <>
-__device__ __forceinline__ void codelet<3>(float2* a, float sg) {
-  const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
-  const float2 t = cadd(a[1], a[2]);
-  const float2 d = mul_i(cscale(csub(a[1], a[2]), h), sg);
-  const float2 b = make_float2(a[0].x - 0.5f * t.x, a[0].y - 0.5f * t.y);
-  a[0] = cadd(a[0], t);
-  a[1] = cadd(b, d);
-  a[2] = csub(b, d);
-}
+struct Codelet<3> {
+  __device__ static __forceinline__ void run(float2* a, float sg) {
+    const float h = 0.86602540378443864676f;  // sin(2 pi / 3)
+    const float2 t = cadd(a[1], a[2]);
+    const float2 d = mul_i(cscale(csub(a[1], a[2]), h), sg);
+    const float2 b = make_float2(a[0].x - 0.5f * t.x, a[0].y - 0.5f * t.y);
+    a[0] = cadd(a[0], t);
+    a[1] = cadd(b, d);
+    a[2] = csub(b, d);
+  }
+};
 
 template <>
-__device__ __forceinline__ void codelet<5>(float2* a, float sg) {
-  const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
-  const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
-  const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
-  const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
-  const float2 t1 = cadd(a[1], a[4]), d1 = csub(a[1], a[4]);
-  const float2 t2 = cadd(a[2], a[3]), d2 = csub(a[2], a[3]);
-  const float2 r1 = make_float2(a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y);
-  const float2 r2 = make_float2(a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y);
-  const float2 i1 = mul_i(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), sg);
-  const float2 i2 = mul_i(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), sg);
-  a[0] = make_float2(a[0].x + t1.x + t2.x, a[0].y + t1.y + t2.y);
-  a[1] = cadd(r1, i1);
-  a[4] = csub(r1, i1);
-  a[2] = cadd(r2, i2);
-  a[3] = csub(r2, i2);
+struct Codelet<5> {
+  __device__ static __forceinline__ void run(float2* a, float sg) {
+    const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    const float2 t1 = cadd(a[1], a[4]), d1 = csub(a[1], a[4]);
+    const float2 t2 = cadd(a[2], a[3]), d2 = csub(a[2], a[3]);
+    const float2 r1 = make_float2(a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 r2 = make_float2(a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y);
+    const float2 i1 = mul_i(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y), sg);
+    const float2 i2 = mul_i(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y), sg);
+    a[0] = make_float2(a[0].x + t1.x + t2.x, a[0].y + t1.y + t2.y);
+    a[1] = cadd(r1, i1);
+    a[4] = csub(r1, i1);
+    a[2] = cadd(r2, i2);
+    a[3] = csub(r2, i2);
+  }
+};
+
+// Composite R = R1 * R2 (Cooley-Tukey in registers): inputs n = R2 n1 + n2,
+// outputs k = k1 + R1 k2, inner twiddles e^{sg 2 pi i n2 k1 / R}.
+template <int R1, int R2>
+struct Composite {
+  __device__ static __forceinline__ void run(float2* a, float sg) {
+    constexpr int R = R1 * R2;
+    float2 t[R];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      float2 u[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) u[n1] = a[R2 * n1 + n2];
+      Codelet<R1>::run(u, sg);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const int e = (n2 * k1) % R;
+        if (e == 0) {
+          t[n2 * R1 + k1] = u[k1];
+        } else {
+          t[n2 * R1 + k1] = cmul(u[k1], make_float2(root_cos<R>(e), sg * root_sin<R>(e)));
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      float2 u[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) u[n2] = t[n2 * R1 + k1];
+      Codelet<R2>::run(u, sg);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) a[k1 + R1 * k2] = u[k2];
+    }
+  }
+};
+
+template <>
+struct Codelet<8> : Composite<2, 4> {};
+template <>
+struct Codelet<9> : Composite<3, 3> {};
+template <>
+struct Codelet<10> : Composite<2, 5> {};
+template <>
+struct Codelet<16> : Composite<4, 4> {};
+
+// One in-place Stockham pass of radix R over FGW sequences of length N held
+// in LDS; P is the product of the radices of the earlier passes.  Every
+// thread first gathers the inputs of all its butterflies into registers,
+// then (after a barrier) overwrites the buffer with their outputs.
+template <int N, int R, int P>
+__device__ __forceinline__ void pass_inplace(float2* buf, const float2* __restrict__ tw, float sg) {
+  constexpr int NB = N / R;
+  constexpr int TOT = FGW * NB;
+  constexpr int PER = (TOT + NT - 1) / NT;
+  constexpr int TS = N / (P * R);
+  float2 v[PER][R];
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int bi = threadIdx.x + b * NT;
+    if (bi < TOT) {
+      const int f = bi / NB;
+      const int t = bi - f * NB;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[b][q] = buf[f * N + t + q * NB];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < PER; ++b) {
+    const int bi = threadIdx.x + b * NT;
+    if (bi < TOT) {
+      const int f = bi / NB;
+      const int t = bi - f * NB;
+      const int k = t % P;
+      if (P > 1 && k != 0) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 w = tw[q * k * TS];
+          if (sg > 0.f) w.y = -w.y;  // table holds e^{-2 pi i j / N}
+          v[b][q] = cmul(v[b][q], w);
+        }
+      }
+      Codelet<R>::run(v[b], sg);
+      const int ob = f * N + (t - k) * R + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[ob + q * P] = v[b][q];
+    }
+  }
+  __syncthreads();
 }
 
-// One radix-R Stockham butterfly: inputs src[tt + q*nb], twiddled by
-// w^(q*kk) with w = e^{sg 2 pi i / (p R)}, outputs dst[(tt-kk)*R + kk + q*p].
+template <int N, int R1, int R2, int R3>
+struct FastFFT {
+  static constexpr int kLdsComplex = FGW * N;  // single in-place buffer
+  __device__ static __forceinline__ float2* run(float2* buf, const DftArgs&, const float2* __restrict__ tw,
+                                                float sg) {
+    static_assert(R1 * R2 * R3 == N, "radix plan");
+    pass_inplace<N, R1, 1>(buf, tw, sg);
+    pass_inplace<N, R2, R1>(buf, tw, sg);
+    if constexpr (R3 > 1) pass_inplace<N, R3, R1 * R2>(buf, tw, sg);
+    return buf;
+  }
+};
+
+// Runtime radices (4, 2, 3, 5), ping-pong buffers: any N = 2^a 3^b 5^c.
 template <int R>
-__device__ __forceinline__ void butterfly(const float2* __restrict__ src, float2* __restrict__ dst,
-                                          int tt, int nb, int kk, int p, int tstride,
-                                          const float2* __restrict__ tw, float sg) {
+__device__ __forceinline__ void pingpong_bfly(const float2* __restrict__ src, float2* __restrict__ dst, int tt,
+                                              int nb, int kk, int p, int tstride, const float2* __restrict__ tw,
+                                              float sg) {
   float2 a[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) a[q] = src[tt + q * nb];
@@ -98,163 +269,226 @@ __device__ __forceinline__ void butterfly(const float2* __restrict__ src, float2
 #pragma unroll
     for (int q = 1; q < R; ++q) {
       float2 w = tw[q * kk * tstride];
-      w.y *= sg < 0.f ? 1.f : -1.f;  // table holds e^{-2 pi i j / N}
+      if (sg > 0.f) w.y = -w.y;
       a[q] = cmul(a[q], w);
     }
   }
-  codelet<R>(a, sg);
+  Codelet<R>::run(a, sg);
   const int ob = (tt - kk) * R + kk;
 #pragma unroll
   for (int q = 0; q < R; ++q) dst[ob + q * p] = a[q];
 }
 
-// fg independent complex FFTs of length N held in LDS at src (fg * N
-// entries); returns the buffer holding the result.  sg = -1: forward.
-__device__ float2* fft_lds(float2* src, float2* dst, const DftArgs& a, const float2* __restrict__ tw,
-                           float sg) {
-  const int N = a.nlon;
-  int p = 1;
-  for (int s = 0; s < a.nstages; ++s) {
-    const int R = a.radix[s];
-    const int nb = N / R;
-    const int tstride = N / (p * R);
-    const int total = a.fg * nb;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-      const int f = t / nb;
-      const int tt = t - f * nb;
-      const int kk = tt % p;
-      const float2* in = src + f * N;
-      float2* out = dst + f * N;
-      switch (R) {
-        case 4: butterfly<4>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
-        case 2: butterfly<2>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
-        case 3: butterfly<3>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
-        default: butterfly<5>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
+struct GenericFFT {
+  __device__ static float2* run(float2* src, const DftArgs& a, const float2* __restrict__ tw, float sg) {
+    const int N = a.nlon;
+    float2* dst = src + FGW * N;
+    int p = 1;
+    for (int s = 0; s < a.nstages; ++s) {
+      const int R = a.radix[s];
+      const int nb = N / R;
+      const int tstride = N / (p * R);
+      const int total = FGW * nb;
+      for (int t = threadIdx.x; t < total; t += NT) {
+        const int f = t / nb;
+        const int tt = t - f * nb;
+        const int kk = tt % p;
+        const float2* in = src + f * N;
+        float2* out = dst + f * N;
+        switch (R) {
+          case 4: pingpong_bfly<4>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
+          case 2: pingpong_bfly<2>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
+          case 3: pingpong_bfly<3>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
+          default: pingpong_bfly<5>(in, out, tt, nb, kk, p, tstride, tw, sg); break;
+        }
       }
+      __syncthreads();
+      float2* t = src;
+      src = dst;
+      dst = t;
+      p *= R;
     }
-    __syncthreads();
-    float2* t = src;
-    src = dst;
-    dst = t;
-    p *= R;
+    return src;
   }
-  return src;
+};
+
+// Workgroup -> (field group g, ring kk, half hh).  Items are ordered
+// (g, kk, hh) and each XCD (the hardware deals workgroups to the 8 XCDs
+// round-robin) receives one contiguous slice of that order.
+struct Item {
+  int g, kk, hh;
+  bool valid;
+};
+__device__ __forceinline__ Item decode_item(const DftArgs& a) {
+  const int per = (a.nitems + 7) / 8;
+  const int slot = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  Item it;
+  it.valid = slot < a.nitems;
+  const int two_nk = 2 * a.nk;
+  it.g = slot / two_nk;
+  const int rem = slot - it.g * two_nk;
+  it.kk = rem >> 1;
+  it.hh = rem & 1;
+  if (it.valid && 8 * it.g + 4 * it.hh >= a.F) it.valid = false;
+  return it;
 }
 
-__global__ __launch_bounds__(256) void dft_forward_kernel(DftArgs a, const float* __restrict__ x,
-                                                          float* __restrict__ W,
-                                                          const float2* __restrict__ tw,
-                                                          const float* __restrict__ ring_scale) {
+__device__ __forceinline__ size_t wrow(const DftArgs& a, int m, int p, int g, int kk) {
+  return ((static_cast<size_t>(2 * m + p) * a.G + g) * a.kpad + kk) * 16;
+}
+
+template <class FFT>
+__global__ __launch_bounds__(NT) void dft_forward_kernel(DftArgs a, const float* __restrict__ x,
+                                                         float* __restrict__ W, const float2* __restrict__ tw,
+                                                         const float* __restrict__ ring_scale) {
   extern __shared__ float2 lds[];
+  const Item it = decode_item(a);
+  if (!it.valid) return;
   const int N = a.nlon;
-  float2* b0 = lds;
-  float2* b1 = lds + a.fg * N;
-  const int kk = blockIdx.x;
+  const int kk = it.kk;
   const int ks = a.nlat - 1 - kk;
   const bool eq = (ks == kk);
-  const int f0 = blockIdx.y * a.fg;
-  for (int idx = threadIdx.x; idx < a.fg * N; idx += blockDim.x) {
-    const int f = idx / N;
-    const int j = idx - f * N;
-    const int fi = f0 + f;
-    float re = 0.f, im = 0.f;
-    if (fi < a.F) {
-      re = x[(static_cast<size_t>(fi) * a.nlat + kk) * N + j];
-      if (!eq) im = x[(static_cast<size_t>(fi) * a.nlat + ks) * N + j];
+  const int f0 = 8 * it.g + 4 * it.hh;
+  // load 4 fields x 2 rings, packed as complex (north, mirrored ring)
+  const int nq = N / 4;
+  if ((N & 3) == 0) {
+    for (int idx = threadIdx.x; idx < FGW * nq; idx += NT) {
+      const int fl = idx / nq;
+      const int j = 4 * (idx - fl * nq);
+      const int fi = f0 + fl;
+      float4 vn = make_float4(0.f, 0.f, 0.f, 0.f), vs = vn;
+      if (fi < a.F) {
+        vn = *reinterpret_cast<const float4*>(x + (static_cast<size_t>(fi) * a.nlat + kk) * N + j);
+        if (!eq) vs = *reinterpret_cast<const float4*>(x + (static_cast<size_t>(fi) * a.nlat + ks) * N + j);
+      }
+      float2* d = lds + fl * N + j;
+      d[0] = make_float2(vn.x, vs.x);
+      d[1] = make_float2(vn.y, vs.y);
+      d[2] = make_float2(vn.z, vs.z);
+      d[3] = make_float2(vn.w, vs.w);
     }
-    b0[idx] = make_float2(re, im);
+  } else {
+    for (int idx = threadIdx.x; idx < FGW * N; idx += NT) {
+      const int fl = idx / N;
+      const int j = idx - fl * N;
+      const int fi = f0 + fl;
+      float re = 0.f, im = 0.f;
+      if (fi < a.F) {
+        re = x[(static_cast<size_t>(fi) * a.nlat + kk) * N + j];
+        if (!eq) im = x[(static_cast<size_t>(fi) * a.nlat + ks) * N + j];
+      }
+      lds[idx] = make_float2(re, im);
+    }
   }
   __syncthreads();
-  const float2* Z = fft_lds(b0, b1, a, tw, -1.f);
+  const float2* Z = FFT::run(lds, a, tw, -1.f);
   const float sc = ring_scale[kk];
-  for (int idx = threadIdx.x; idx < a.fg * a.mmax; idx += blockDim.x) {
-    const int f = idx % a.fg;
-    const int m = idx / a.fg;
-    const int fi = f0 + f;
-    if (fi >= a.F) continue;
-    const float2 zm = Z[f * N + m];
-    const float2 zr = Z[f * N + (m == 0 ? 0 : N - m)];
-    // spectra of the two packed real rings
-    const float2 xn = make_float2(0.5f * (zm.x + zr.x), 0.5f * (zm.y - zr.y));
-    const float2 xs = make_float2(0.5f * (zm.y + zr.y), -0.5f * (zm.x - zr.x));
-    float2 S, A;
-    if (eq) {
-      S = cscale(xn, sc);
-      A = make_float2(0.f, 0.f);
-    } else {
-      S = cscale(cadd(xn, xs), sc);
-      A = cscale(csub(xn, xs), sc);
+  for (int m = threadIdx.x; m < a.mmax; m += NT) {
+    float Sv[8], Av[8];
+#pragma unroll
+    for (int fl = 0; fl < FGW; ++fl) {
+      const float2 zm = Z[fl * N + m];
+      const float2 zr = Z[fl * N + (m == 0 ? 0 : N - m)];
+      // spectra of the two packed real rings
+      const float2 xn = make_float2(0.5f * (zm.x + zr.x), 0.5f * (zm.y - zr.y));
+      const float2 xs = make_float2(0.5f * (zm.y + zr.y), -0.5f * (zm.x - zr.x));
+      float2 S, A;
+      if (eq) {
+        S = cscale(xn, sc);
+        A = make_float2(0.f, 0.f);
+      } else {
+        S = cscale(cadd(xn, xs), sc);
+        A = cscale(csub(xn, xs), sc);
+      }
+      if (m == 0) {
+        S.y = 0.f;
+        A.y = 0.f;
+      }
+      Sv[2 * fl] = S.x;
+      Sv[2 * fl + 1] = S.y;
+      Av[2 * fl] = A.x;
+      Av[2 * fl + 1] = A.y;
     }
-    if (m == 0) {
-      S.y = 0.f;
-      A.y = 0.f;
-    }
-    const size_t col = 2 * static_cast<size_t>(fi);
-    const size_t r0 = (static_cast<size_t>(2 * m) * a.kpad + kk) * a.npad + col;
-    const size_t r1 = (static_cast<size_t>(2 * m + 1) * a.kpad + kk) * a.npad + col;
-    *reinterpret_cast<float2*>(W + r0) = S;
-    *reinterpret_cast<float2*>(W + r1) = A;
+    float4* ps = reinterpret_cast<float4*>(W + wrow(a, m, 0, it.g, kk) + 8 * it.hh);
+    float4* pa = reinterpret_cast<float4*>(W + wrow(a, m, 1, it.g, kk) + 8 * it.hh);
+    ps[0] = make_float4(Sv[0], Sv[1], Sv[2], Sv[3]);
+    ps[1] = make_float4(Sv[4], Sv[5], Sv[6], Sv[7]);
+    pa[0] = make_float4(Av[0], Av[1], Av[2], Av[3]);
+    pa[1] = make_float4(Av[4], Av[5], Av[6], Av[7]);
   }
 }
 
-__global__ __launch_bounds__(256) void dft_inverse_kernel(DftArgs a, const float* __restrict__ W,
-                                                          float* __restrict__ x,
-                                                          const float2* __restrict__ tw,
-                                                          const float* __restrict__ ring_scale) {
+template <class FFT>
+__global__ __launch_bounds__(NT) void dft_inverse_kernel(DftArgs a, const float* __restrict__ W,
+                                                         float* __restrict__ x, const float2* __restrict__ tw,
+                                                         const float* __restrict__ ring_scale) {
   extern __shared__ float2 lds[];
+  const Item it = decode_item(a);
+  if (!it.valid) return;
   const int N = a.nlon;
-  float2* b0 = lds;
-  float2* b1 = lds + a.fg * N;
-  const int kk = blockIdx.x;
+  const int kk = it.kk;
   const int ks = a.nlat - 1 - kk;
   const bool eq = (ks == kk);
-  const int f0 = blockIdx.y * a.fg;
-  for (int idx = threadIdx.x; idx < a.fg * N; idx += blockDim.x) b0[idx] = make_float2(0.f, 0.f);
+  const int f0 = 8 * it.g + 4 * it.hh;
+  for (int idx = threadIdx.x; idx < FGW * N; idx += NT) lds[idx] = make_float2(0.f, 0.f);
   __syncthreads();
   const float h = 0.5f * a.c_rest;
-  for (int idx = threadIdx.x; idx < a.fg * a.mmax; idx += blockDim.x) {
-    const int f = idx % a.fg;
-    const int m = idx / a.fg;
-    const int fi = f0 + f;
-    if (fi >= a.F) continue;
-    const size_t col = 2 * static_cast<size_t>(fi);
-    const float2 E = *reinterpret_cast<const float2*>(W + (static_cast<size_t>(2 * m) * a.kpad + kk) * a.npad + col);
-    // order m has odd-parity degrees only when l = m + 1 < lmax; otherwise
-    // the synthesis never writes that plane and it must read as zero
-    const float2 O = (m + 1 < a.lmax)
-        ? *reinterpret_cast<const float2*>(W + (static_cast<size_t>(2 * m + 1) * a.kpad + kk) * a.npad + col)
-        : make_float2(0.f, 0.f);
-    const float2 yn = cadd(E, O);
-    const float2 ys = eq ? make_float2(0.f, 0.f) : csub(E, O);
-    if (m == 0) {
-      b0[f * N] = make_float2(yn.x, ys.x);
-    } else {
-      const float2 hn = cscale(yn, h), hs = cscale(ys, h);
-      b0[f * N + m] = make_float2(hn.x - hs.y, hn.y + hs.x);
-      b0[f * N + N - m] = make_float2(hn.x + hs.y, -hn.y + hs.x);
+  for (int m = threadIdx.x; m < a.mmax; m += NT) {
+    const float4* pe = reinterpret_cast<const float4*>(W + wrow(a, m, 0, it.g, kk) + 8 * it.hh);
+    const float4 e0 = pe[0], e1 = pe[1];
+    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0;
+    // order m has odd-parity degrees only when m + 1 < lmax
+    if (m + 1 < a.lmax) {
+      const float4* po = reinterpret_cast<const float4*>(W + wrow(a, m, 1, it.g, kk) + 8 * it.hh);
+      o0 = po[0];
+      o1 = po[1];
+    }
+    const float Ev[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+    const float Ov[8] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
+#pragma unroll
+    for (int fl = 0; fl < FGW; ++fl) {
+      const float2 E = make_float2(Ev[2 * fl], Ev[2 * fl + 1]);
+      const float2 O = make_float2(Ov[2 * fl], Ov[2 * fl + 1]);
+      const float2 yn = cadd(E, O);
+      const float2 ys = eq ? make_float2(0.f, 0.f) : csub(E, O);
+      if (m == 0) {
+        lds[fl * N] = make_float2(yn.x, ys.x);
+      } else {
+        const float2 hn = cscale(yn, h), hs = cscale(ys, h);
+        lds[fl * N + m] = make_float2(hn.x - hs.y, hn.y + hs.x);
+        lds[fl * N + N - m] = make_float2(hn.x + hs.y, -hn.y + hs.x);
+      }
     }
   }
   __syncthreads();
-  const float2* Z = fft_lds(b0, b1, a, tw, 1.f);
+  const float2* Z = FFT::run(lds, a, tw, 1.f);
   const float sc = ring_scale[kk];
-  for (int idx = threadIdx.x; idx < a.fg * N; idx += blockDim.x) {
-    const int f = idx / N;
-    const int j = idx - f * N;
-    const int fi = f0 + f;
-    if (fi >= a.F) continue;
-    const float2 z = Z[idx];
-    x[(static_cast<size_t>(fi) * a.nlat + kk) * N + j] = z.x * sc;
-    if (!eq) x[(static_cast<size_t>(fi) * a.nlat + ks) * N + j] = z.y * sc;
+  const int nq = N / 4;
+  if ((N & 3) == 0) {
+    for (int idx = threadIdx.x; idx < FGW * nq; idx += NT) {
+      const int fl = idx / nq;
+      const int j = 4 * (idx - fl * nq);
+      const int fi = f0 + fl;
+      if (fi >= a.F) continue;
+      const float2* z = Z + fl * N + j;
+      const float2 z0 = z[0], z1 = z[1], z2 = z[2], z3 = z[3];
+      *reinterpret_cast<float4*>(x + (static_cast<size_t>(fi) * a.nlat + kk) * N + j) =
+          make_float4(z0.x * sc, z1.x * sc, z2.x * sc, z3.x * sc);
+      if (!eq)
+        *reinterpret_cast<float4*>(x + (static_cast<size_t>(fi) * a.nlat + ks) * N + j) =
+            make_float4(z0.y * sc, z1.y * sc, z2.y * sc, z3.y * sc);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < FGW * N; idx += NT) {
+      const int fl = idx / N;
+      const int j = idx - fl * N;
+      const int fi = f0 + fl;
+      if (fi >= a.F) continue;
+      const float2 z = Z[idx];
+      x[(static_cast<size_t>(fi) * a.nlat + kk) * N + j] = z.x * sc;
+      if (!eq) x[(static_cast<size_t>(fi) * a.nlat + ks) * N + j] = z.y * sc;
+    }
   }
-}
-
-int pick_fg(int n, int F) {
-  // two ping-pong buffers of fg * n complex floats within 64 KiB of LDS
-  int fg = 65536 / (16 * n);
-  if (fg > 16) fg = 16;
-  if (fg > F) fg = F;
-  if (fg < 1) fg = 1;
-  return fg;
 }
 
 DftArgs make_args(const SegGeom& g, const DftPlan& dp) {
@@ -266,11 +500,48 @@ DftArgs make_args(const SegGeom& g, const DftPlan& dp) {
   a.nk = g.nk;
   a.F = g.F;
   a.kpad = g.kpad;
-  a.npad = g.npad;
-  a.fg = pick_fg(g.nlon, g.F);
+  a.G = g.groups;
+  a.nitems = g.groups * g.nk * 2;
   a.nstages = dp.nstages;
   for (int i = 0; i < kMaxRadices; ++i) a.radix[i] = dp.radix[i];
   return a;
+}
+
+template <bool FORWARD, class FFT>
+hipError_t launch_with(const DftArgs& a, size_t lds_bytes, const float* in, float* out, const float2* tw,
+                       const float* scale, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((a.nitems + 7) / 8 * 8);
+  if (FORWARD) {
+    auto k = dft_forward_kernel<FFT>;
+    if (lds_bytes > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds_bytes, st, a, in, out, tw, scale);
+  } else {
+    auto k = dft_inverse_kernel<FFT>;
+    if (lds_bytes > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds_bytes, st, a, in, out, tw, scale);
+  }
+  return hipGetLastError();
+}
+
+template <bool FORWARD>
+hipError_t dispatch(const DftArgs& a, const float* in, float* out, const float2* tw, const float* scale,
+                    hipStream_t st) {
+  const size_t one = static_cast<size_t>(FGW) * a.nlon * sizeof(float2);
+  switch (a.nlon) {
+    case 1440: return launch_with<FORWARD, FastFFT<1440, 9, 10, 16>>(a, one, in, out, tw, scale, st);
+    case 720: return launch_with<FORWARD, FastFFT<720, 9, 5, 16>>(a, one, in, out, tw, scale, st);
+    case 360: return launch_with<FORWARD, FastFFT<360, 9, 5, 8>>(a, one, in, out, tw, scale, st);
+    case 64: return launch_with<FORWARD, FastFFT<64, 4, 16, 1>>(a, one, in, out, tw, scale, st);
+    default: return launch_with<FORWARD, GenericFFT>(a, 2 * one, in, out, tw, scale, st);
+  }
 }
 
 }  // namespace
@@ -294,10 +565,7 @@ bool make_dft_plan(int n, DftPlan* p) {
 hipError_t launch_dft_forward(const SegGeom& g, const DftPlan& dp, const float* x, float* W,
                               const float2* tw, const float* ring_scale, hipStream_t st) {
   DftArgs a = make_args(g, dp);
-  dim3 grid(g.nk, (g.F + a.fg - 1) / a.fg);
-  const size_t lds = 2 * static_cast<size_t>(a.fg) * g.nlon * sizeof(float2);
-  hipLaunchKernelGGL(dft_forward_kernel, grid, dim3(256), lds, st, a, x, W, tw, ring_scale);
-  return hipGetLastError();
+  return dispatch<true>(a, x, W, tw, ring_scale, st);
 }
 
 hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* W, float* x,
@@ -305,10 +573,7 @@ hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* 
                               hipStream_t st) {
   DftArgs a = make_args(g, dp);
   a.c_rest = c_rest;
-  dim3 grid(g.nk, (g.F + a.fg - 1) / a.fg);
-  const size_t lds = 2 * static_cast<size_t>(a.fg) * g.nlon * sizeof(float2);
-  hipLaunchKernelGGL(dft_inverse_kernel, grid, dim3(256), lds, st, a, W, x, tw, ring_scale);
-  return hipGetLastError();
+  return dispatch<false>(a, W, x, tw, ring_scale, st);
 }
 
 }  // namespace sht

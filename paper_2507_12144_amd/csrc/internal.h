@@ -11,13 +11,10 @@ namespace sht {
 // Rows of the folded Legendre table are padded per (m, parity) to a multiple
 // of this, so that every row tile of the contraction kernels is full.
 constexpr int kRowPad = 64;
-// Ring (contraction K) dimension of the table and workspace is padded to a
-// multiple of this.
-constexpr int kRingPad = 32;
-// Column (field) dimension of the workspace is padded to a multiple of this.
-constexpr int kColPad = 64;
 // Longest ring DFT supported (LDS budget of the DFT kernels).
-constexpr int kMaxNlon = 4096;
+constexpr int kMaxNlon = 2048;
+// Most northern rings (incl. the equator) the contraction kernels hold.
+constexpr int kMaxRings = 384;
 constexpr int kMaxRadices = 16;
 
 // Storage of the Legendre table / data operands of the contraction.
@@ -28,8 +25,8 @@ struct SegGeom {
   int nlat, nlon, lmax, mmax;
   int F;          // fields = batch * channels
   int nk;         // northern rings incl. the equator: (nlat + 1) / 2
-  int kpad;       // nk rounded up to kRingPad
-  int npad;       // 2F rounded up to kColPad (workspace row length, floats)
+  int kpad;       // nk rounded up to a ring count the contraction kernels hold
+  int groups;     // field groups of 8: ceil(F / 8)
   bool has_equator;  // nlat odd
 };
 
@@ -54,7 +51,7 @@ bool make_dft_plan(int n, DftPlan* p);
 
 // Forward ring DFT of the ring pairs (k, nlat-1-k), k < nk, multiplied by
 // ring_scale[k], folded into symmetric/antisymmetric parts and written to
-// the workspace W[m][p][k][col] (float32 complex pairs at col = 2f, 2f+1).
+// the workspace W[m][p][g][k][16] (field f = 8g + i at floats 2i, 2i+1).
 hipError_t launch_dft_forward(const SegGeom& g, const DftPlan& dp, const float* x, float* W,
                               const float2* tw, const float* ring_scale, hipStream_t st);
 // Inverse: reads E = W[m][0], O = W[m][1], north = E + O, south = E - O,
@@ -65,25 +62,32 @@ hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* 
                               hipStream_t st);
 
 // ---- legendre.hip --------------------------------------------------------
-// Tile lists: int4 {m, parity, row0, 0} for analysis (row tiles of the
-// parity block) and {m, parity, k0, 0} for synthesis (ring tiles).
+// Work lists: 8 slices (one per XCD) of work_per entries, padded with
+// {-1, -1}; analysis items are {m, column chunk}, synthesis items
+// {m, 2 * column chunk + ring half}.  ncb = field groups per column chunk.
 struct LegArgs {
   SegGeom g;
   const void* table;
   size_t plane_stride;
   const int64_t* row_off;
   const int* rows_pad;
-  const int4* tiles;
-  int ntiles;
+  const int2* work;
+  int work_per;
+  const int2* work_syn;
+  int work_syn_per;
+  int ncb;
 };
-// y[f][l][m] = mscale_m * sum_k P[m][p][i][k] W[m][p][k][2f..]   (l = m + p + 2i)
+// Ring padding the contraction kernels support for nk rings (-1: none).
+int legendre_ring_pad(int nk);
+// Field groups per column chunk for a segment with `groups` groups.
+int legendre_ncb(int groups);
+// y[f][l][m] = mscale_m sum_k P[m][p][i][k] W[m][p][g][k][..] (l = m + p + 2i),
+// mscale_0 = 1, mscale_m = c_rest; y[f][l][m] = 0 for l < m.
 hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y,
                                     float c_rest, hipStream_t stream);
-// W[m][p][k][2f..] = sum_i P[m][p][i][k] y[f][m + p + 2i][m]
+// W[m][p][g][k][..] = sum_i P[m][p][i][k] y[f][m + p + 2i][m]
 hipError_t launch_legendre_synthesis(const LegArgs& a, Storage st, const float2* y, float* W,
                                      hipStream_t stream);
-// y[f][l][m] = 0 for l < m.
-hipError_t launch_zero_upper(const SegGeom& g, float2* y, hipStream_t stream);
 
 // ---- mix.hip -------------------------------------------------------------
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
