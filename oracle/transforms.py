@@ -53,39 +53,42 @@ def _ring_synth(Y, nlon, c_rest):
 
 
 def _legendre_analysis(X, lmax, x, sin_t):
-    """out[..., l, m] = sum_k P^_l^m(x_k) X[..., k, m] for l >= m, else 0."""
+    """out[..., l, m] = sum_k P^_l^m(x_k) X[..., k, m] for l >= m, else 0.
+
+    The data are moved once to order-major layout so that each order's
+    product reads contiguous memory; the arithmetic is one matrix product
+    per order m."""
     lead = X.shape[:-2]
     nlat, mmax = X.shape[-2], X.shape[-1]
-    out = np.zeros(lead + (lmax, mmax), dtype=np.complex128)
-    Xr = X.real.reshape(-1, nlat, mmax)
-    Xi = X.imag.reshape(-1, nlat, mmax)
-    o = out.reshape(-1, lmax, mmax)
+    Xr = np.ascontiguousarray(np.moveaxis(X.real.reshape(-1, nlat, mmax), -1, 0))  # (mmax, F, nlat)
+    Xi = np.ascontiguousarray(np.moveaxis(X.imag.reshape(-1, nlat, mmax), -1, 0))
+    F = Xr.shape[1]
+    out = np.zeros((mmax, F, lmax), dtype=np.complex128)
     for m, rows in iter_orders(lmax, mmax, x, sin_t):
         if rows.shape[0] == 0:
             continue
         # (F, nlat) @ (nlat, lmax - m)
-        re = np.ascontiguousarray(Xr[:, :, m]) @ rows.T
-        im = np.ascontiguousarray(Xi[:, :, m]) @ rows.T
-        o[:, m:, m] = re + 1j * im
-    return out
+        out[m, :, m:].real = Xr[m] @ rows.T
+        out[m, :, m:].imag = Xi[m] @ rows.T
+    return np.moveaxis(out, 0, -1).reshape(lead + (lmax, mmax))
 
 
 def _legendre_synthesis(a, nlat, x, sin_t):
-    """Y[..., k, m] = sum_{l=m}^{lmax-1} P^_l^m(x_k) a[..., l, m]."""
+    """Y[..., k, m] = sum_{l=m}^{lmax-1} P^_l^m(x_k) a[..., l, m] (one matrix
+    product per order m, on order-major data)."""
     lead = a.shape[:-2]
     lmax, mmax = a.shape[-2], a.shape[-1]
-    Y = np.zeros(lead + (nlat, mmax), dtype=np.complex128)
-    ar = a.real.reshape(-1, lmax, mmax)
-    ai = a.imag.reshape(-1, lmax, mmax)
-    y = Y.reshape(-1, nlat, mmax)
+    ar = np.ascontiguousarray(np.moveaxis(a.real.reshape(-1, lmax, mmax), -1, 0))  # (mmax, F, lmax)
+    ai = np.ascontiguousarray(np.moveaxis(a.imag.reshape(-1, lmax, mmax), -1, 0))
+    F = ar.shape[1]
+    Y = np.zeros((mmax, F, nlat), dtype=np.complex128)
     for m, rows in iter_orders(lmax, mmax, x, sin_t):
         if rows.shape[0] == 0:
             continue
         # (F, lmax - m) @ (lmax - m, nlat)
-        re = np.ascontiguousarray(ar[:, m:, m]) @ rows
-        im = np.ascontiguousarray(ai[:, m:, m]) @ rows
-        y[:, :, m] = re + 1j * im
-    return Y
+        Y[m].real = ar[m, :, m:] @ rows
+        Y[m].imag = ai[m, :, m:] @ rows
+    return np.moveaxis(Y, 0, -1).reshape(lead + (nlat, mmax))
 
 
 def _check_spec(lmax, mmax, nlon):

@@ -62,6 +62,16 @@ bool only_small_primes(int n) {
   return n == 1;
 }
 
+// bf16 planes of the table (0: float32 table).
+int storage_planes(Storage s) {
+  switch (s) {
+    case Storage::BF16: return 1;
+    case Storage::BF16X2: return 2;
+    case Storage::BF16X3: return 3;
+    default: return 0;
+  }
+}
+
 Storage storage_of(sht_precision p) {
   switch (p) {
     case SHT_PREC_BF16: return Storage::BF16;
@@ -69,16 +79,6 @@ Storage storage_of(sht_precision p) {
     case SHT_PREC_BF16X3: return Storage::BF16X3;
     default: return Storage::F32;
   }
-}
-
-size_t storage_bytes_per_entry(Storage s) {
-  switch (s) {
-    case Storage::F32: return 4;
-    case Storage::BF16: return 2;
-    case Storage::BF16X2: return 4;
-    case Storage::BF16X3: return 6;
-  }
-  return 4;
 }
 
 struct Segment {
@@ -92,10 +92,9 @@ struct Segment {
   float* scale_sht = nullptr;  // (2 pi / nlon) w_k, k < nk
   float* scale_one = nullptr;  // 1
   float2* tw = nullptr;        // e^{-2 pi i j / nlon}
-  int64_t* row_off = nullptr;
-  int* rows_pad = nullptr;
-  void* table = nullptr;
-  size_t plane_stride = 0;
+  void* tab_ana = nullptr;     // Legendre table, analysis fragment order
+  void* tab_syn = nullptr;     // Legendre table, synthesis fragment order
+  int64_t* tab_off = nullptr;  // [mmax]
   int2* worklist = nullptr;
   int work_per = 0;
   int2* worklist_syn = nullptr;
@@ -151,7 +150,7 @@ namespace sht {
 namespace {
 
 void free_segment(Segment& s) {
-  void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.row_off, s.rows_pad, s.table,
+  void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.tab_ana, s.tab_syn, s.tab_off,
                   s.worklist, s.worklist_syn, s.work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -216,18 +215,35 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   }
   if ((rc = upload(&S.tw, tw, st, "twiddle upload")) != SHT_OK) return rc;
 
-  // folded table layout: per m two parity blocks of rows_pad[m] rows
-  std::vector<int64_t> row_off(d.mmax);
-  std::vector<int> rows_pad(d.mmax);
-  int64_t rows = 0;
-  for (int m = 0; m < d.mmax; ++m) {
-    const int n0 = (d.lmax - m + 1) / 2;
-    rows_pad[m] = static_cast<int>(round_up(n0 > 0 ? n0 : 1, kRowPad));
-    row_off[m] = rows;
-    rows += 2LL * rows_pad[m];
+  // Legendre tables in the two MFMA fragment orders.  float32: per order m,
+  // two parity blocks of ceil(ceil((lmax-m)/2)/16) 16-row blocks of kpad
+  // rings; bf16 forms: 32-row blocks, `planes` bf16 values per entry.
+  {
+    const int planes = storage_planes(storage);
+    const int rows_blk = planes ? 32 : 16;
+    std::vector<int64_t> off(d.mmax);
+    int64_t n = 0;
+    for (int m = 0; m < d.mmax; ++m) {
+      off[m] = n;
+      const int nb = (((d.lmax - m + 1) >> 1) + rows_blk - 1) / rows_blk;
+      n += 2LL * nb * rows_blk * g.kpad * (planes ? planes : 1);
+    }
+    if ((rc = upload(&S.tab_off, off, st, "table offsets")) != SHT_OK) return rc;
+    const size_t tbytes = static_cast<size_t>(n) * (planes ? sizeof(uint16_t) : sizeof(float));
+    for (void** t : {&S.tab_ana, &S.tab_syn}) {
+      e = dev_alloc(t, tbytes);
+      if (e != hipSuccess) return hip_fail(e, "Legendre table allocation");
+      e = hipMemsetAsync(*t, 0, tbytes, st);
+      if (e != hipSuccess) return hip_fail(e, "table clear");
+    }
+    if (planes)
+      e = launch_frag_table_bf16(g, planes, S.x, S.s, S.tab_off, static_cast<uint16_t*>(S.tab_ana),
+                                 static_cast<uint16_t*>(S.tab_syn), st);
+    else
+      e = launch_frag_table(g, S.x, S.s, S.tab_off, static_cast<float*>(S.tab_ana), static_cast<float*>(S.tab_syn),
+                            st);
+    if (e != hipSuccess) return hip_fail(e, "Legendre table kernel");
   }
-  if ((rc = upload(&S.row_off, row_off, st, "table offsets")) != SHT_OK) return rc;
-  if ((rc = upload(&S.rows_pad, rows_pad, st, "table offsets")) != SHT_OK) return rc;
 
   // contraction work list: chunks of 16 consecutive m dealt round-robin to
   // the 8 XCDs, each XCD's chunks in ascending m (largest work first)
@@ -255,16 +271,6 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
     }
   }
 
-  const size_t entries = static_cast<size_t>(rows) * g.kpad;
-  S.plane_stride = entries;
-  const size_t tbytes = entries * storage_bytes_per_entry(storage);
-  e = dev_alloc(&S.table, tbytes);
-  if (e != hipSuccess) return hip_fail(e, "Legendre table allocation");
-  e = hipMemsetAsync(S.table, 0, tbytes, st);
-  if (e != hipSuccess) return hip_fail(e, "table clear");
-  e = launch_table(g, S.x, S.s, S.row_off, S.rows_pad, storage, S.table, S.plane_stride, st);
-  if (e != hipSuccess) return hip_fail(e, "table kernel");
-
   // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
   const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.groups * g.kpad * 16 * sizeof(float);
   e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
@@ -279,10 +285,9 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
 LegArgs leg_args(const Segment& S) {
   LegArgs a{};
   a.g = S.g;
-  a.table = S.table;
-  a.plane_stride = S.plane_stride;
-  a.row_off = S.row_off;
-  a.rows_pad = S.rows_pad;
+  a.tab_ana = S.tab_ana;
+  a.tab_syn = S.tab_syn;
+  a.tab_off = S.tab_off;
   a.work = S.worklist;
   a.work_per = S.work_per;
   a.work_syn = S.worklist_syn;
@@ -354,7 +359,9 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
         });
         if (e == hipSuccess)
           e = timed(plan, K_LEG_ANA, st, [&] {
-            return launch_legendre_analysis(leg_args(S), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
+            const int planes = storage_planes(plan->storage);
+            return planes ? launch_legendre_analysis_bf16(leg_args(S), planes, S.work, y, fwd ? 1.f : 2.f, st)
+                          : launch_legendre_analysis(leg_args(S), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
           });
         break;
       }
@@ -364,7 +371,9 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
         float* x = static_cast<float*>(out) + S.grid_off;
         const bool inv = (op == Op::ISHT);
         e = timed(plan, K_LEG_SYN, st, [&] {
-          return launch_legendre_synthesis(leg_args(S), plan->storage, y, S.work, st);
+          const int planes = storage_planes(plan->storage);
+          return planes ? launch_legendre_synthesis_bf16(leg_args(S), planes, y, S.work, st)
+                        : launch_legendre_synthesis(leg_args(S), plan->storage, y, S.work, st);
         });
         if (e == hipSuccess)
           e = timed(plan, K_DFT_INV, st, [&] {
@@ -401,7 +410,6 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
     sht_status s = validate_desc(descs[i], i);
     if (s != SHT_OK) return s;
   }
-  if (prec != SHT_PREC_FP32) return fail(SHT_ERR_UNSUPPORTED, "precision %d not built yet", static_cast<int>(prec));
   // --- first HIP call below this line ---
   auto* p = new (std::nothrow) sht_plan_s();
   if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");

@@ -1,7 +1,8 @@
 // Plan-time float64 kernels: latitude nodes and quadrature weights (App. B.1)
-// and the folded table of orthonormal associated Legendre functions
-// (App. B.3, eq. spherical_harmonics).  These are the only float64 kernels
-// of the library; everything on the transform path is float32 / bf16.
+// and the table of orthonormal associated Legendre functions by their
+// three-term recurrence (App. B.3, eq. spherical_harmonics).  These are the
+// only float64 kernels; every operation of the transforms themselves is
+// float32 (or bf16 on the matrix cores).
 #include "internal.h"
 #include "bf16.h"
 
@@ -78,46 +79,112 @@ __global__ void grid_kernel(int nlat, int kind, double* __restrict__ xo, double*
   wo[k] = w;
 }
 
-template <int PLANES>
-__device__ inline void store_bf16_planes(uint16_t* t, size_t idx, size_t plane_stride, double v) {
-  double r = v;
-#pragma unroll
-  for (int p = 0; p < PLANES; ++p) {
-    const uint16_t b = bf16_rn_from_double(r);
-    t[idx + p * plane_stride] = b;
-    r -= bf16_bits_to_double(b);  // exact in float64
-  }
-}
-
-// One thread per (ring k < nk, order m).  The recurrence in l runs in
-// float64 and every value is rounded once to the storage form:
-//   P^_m^m     = -sqrt((2m+1)/(2m)) sin t P^_{m-1}^{m-1},  P^_0^0 = 1/sqrt(4 pi)
+// Legendre table in MFMA fragment order.  One thread per (ring k < nk,
+// order m) runs the float64 recurrence of eq. spherical_harmonics
+//   P^_0^0 = 1/sqrt(4 pi),  P^_m^m = -sqrt((2m+1)/(2m)) sin t P^_{m-1}^{m-1}
 //   P^_{m+1}^m = sqrt(2m+3) x P^_m^m
-//   P^_l^m     = a_lm (x P^_{l-1}^m - b_lm P^_{l-2}^m)
-//   a_lm = sqrt((4l^2-1)/(l^2-m^2)), b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1))
-// Row of (m, l): row_off[m] + ((l-m)&1) * rows_pad[m] + (l-m)/2.
-template <int MODE>  // 0: f32, 1..3: bf16 planes
-__global__ void table_kernel(SegGeom g, const double* __restrict__ xs, const double* __restrict__ ss,
-                             const int64_t* __restrict__ row_off, const int* __restrict__ rows_pad,
-                             void* __restrict__ table, size_t plane_stride) {
+//   P^_l^m = a_lm (x P^_{l-1}^m - b_lm P^_{l-2}^m)
+//   a_lm = sqrt((4l^2-1)/(l^2-m^2)),  b_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1))
+// and rounds every value once to float32.  Degree l of order m has parity
+// p = (l-m) & 1 and row i = (l-m) >> 1 of its parity block; rows come in
+// blocks of 16 (ib = i / 16).  Each value is written to two tables, laid
+// out so that a wave of the contraction kernels reads its MFMA A operands
+// of four consecutive steps as one contiguous 1 KiB load (16 bytes a lane):
+//  * analysis  (A[i][k], lane = 16 lk + li holds row li, k = lk*KS + 4t + q):
+//      off[m] + ((p*nb + ib)*(KS/4) + t)*256 + (16 lk + li)*4 + q
+//  * synthesis (A[k][i], lane = 16 lk + li holds i = 4s + lk, k = li*KR + 4t + q):
+//      off[m] + (((p*nb + ib)*4 + s)*(KR/4) + t)*256 + (16 lk + li)*4 + q
+// with KS = kpad/4, KR = kpad/16 and nb = ceil(ceil((lmax-m)/2) / 16).
+// Values too small for float64 flush to zero; none of them can grow back to
+// a significant size before l = 768 on the supported grids.
+__global__ void frag_table_kernel(SegGeom g, const double* __restrict__ xs, const double* __restrict__ ss,
+                                  const int64_t* __restrict__ off, float* __restrict__ ta,
+                                  float* __restrict__ tsyn) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   if (k >= g.nk || m >= g.mmax) return;
-  const double x = xs[k];
-  const double s = ss[k];
-  double pmm = 1.0 / sqrt(4.0 * kPi);
-  for (int i = 1; i <= m; ++i) pmm = -sqrt((2.0 * i + 1.0) / (2.0 * i)) * s * pmm;
-  const int64_t base = row_off[m];
-  const int rp = rows_pad[m];
+  const int KS = g.kpad / 4, KR = g.kpad / 16;
+  const int nb = (((g.lmax - m + 1) >> 1) + 15) / 16;
+  const size_t base = static_cast<size_t>(off[m]);
+  // position of ring k inside the two fragment layouts
+  const int a_lk = k / KS, a_rem = k - a_lk * KS, a_t = a_rem >> 2, a_q = a_rem & 3;
+  const int s_li = k / KR, s_rem = k - s_li * KR, s_t = s_rem >> 2, s_q = s_rem & 3;
   auto put = [&](int l, double v) {
     const int d = l - m;
-    const size_t idx = static_cast<size_t>(base + (d & 1) * rp + (d >> 1)) * g.kpad + k;
-    if constexpr (MODE == 0) {
-      static_cast<float*>(table)[idx] = __double2float_rn(v);
-    } else {
-      store_bf16_planes<MODE>(static_cast<uint16_t*>(table), idx, plane_stride, v);
+    const int p = d & 1, i = d >> 1, ib = i >> 4, li = i & 15;
+    const float f = __double2float_rn(v);
+    const size_t blk = static_cast<size_t>(p * nb + ib);
+    ta[base + (blk * (KS / 4) + a_t) * 256 + (16 * a_lk + li) * 4 + a_q] = f;
+    const int s = li >> 2, lk = li & 3;
+    tsyn[base + ((blk * 4 + s) * (KR / 4) + s_t) * 256 + (16 * lk + s_li) * 4 + s_q] = f;
+  };
+  const double x = xs[k];
+  const double sn = ss[k];
+  double pmm = 1.0 / sqrt(4.0 * kPi);
+  for (int i = 1; i <= m; ++i) pmm = -sqrt((2.0 * i + 1.0) / (2.0 * i)) * sn * pmm;
+  if (m >= g.lmax) return;
+  put(m, pmm);
+  if (m + 1 >= g.lmax) return;
+  double p2 = pmm;
+  double p1 = sqrt(2.0 * m + 3.0) * x * pmm;
+  put(m + 1, p1);
+  const double mm = static_cast<double>(m) * m;
+  for (int l = m + 2; l < g.lmax; ++l) {
+    const double dl = l;
+    const double a = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - mm));
+    const double b = sqrt(((dl - 1.0) * (dl - 1.0) - mm) / (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
+    const double p = a * (x * p1 - b * p2);
+    p2 = p1;
+    p1 = p;
+    put(l, p);
+  }
+}
+
+// bf16 planes of the same table for the bf16 matrix-core kernels
+// (v_mfma_f32_16x16x32_bf16: a lane holds 8 consecutive K values).  Each
+// float64 value v is split into NP bf16 planes, each rounded to nearest-even
+// from the float64 residual: hi = bf16(v), next = bf16(v - hi), ...  Rows
+// come in 32-row blocks per parity (nb32 = ceil(ceil((lmax-m)/2) / 32)); per
+// plane and step a wave reads 64 lanes x 8 values = 1 KiB:
+//  * analysis  (16-row sub-blocks, lane 16 lk + li holds row li,
+//    k = lk*KPAD/4 + 8t + e):
+//      off[m] + ((blk16*T8 + t)*NP + plane)*512 + (16 lk + li)*8 + e
+//  * synthesis (lane 16 lk + li holds i = 8 lk + e of the 32-row block,
+//    ring k = li*KR + rb):
+//      off[m] + ((blk32*KR + rb)*NP + plane)*512 + (16 lk + li)*8 + e
+// with T8 = kpad/32 and KR = kpad/16.
+template <int NP>
+__global__ void frag_table_bf16_kernel(SegGeom g, const double* __restrict__ xs, const double* __restrict__ ss,
+                                       const int64_t* __restrict__ off, uint16_t* __restrict__ ta,
+                                       uint16_t* __restrict__ tsyn) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (k >= g.nk || m >= g.mmax) return;
+  const int Q = g.kpad / 4, T8 = g.kpad / 32, KR = g.kpad / 16;
+  const int nb32 = (((g.lmax - m + 1) >> 1) + 31) / 32;
+  const size_t base = static_cast<size_t>(off[m]);
+  const int a_lk = k / Q, a_rem = k - a_lk * Q, a_t = a_rem >> 3, a_e = a_rem & 7;
+  const int s_li = k / KR, s_rb = k - s_li * KR;
+  auto put = [&](int l, double v) {
+    const int d = l - m;
+    const int p = d & 1, i = d >> 1;
+    const size_t blk16 = static_cast<size_t>(p * 2 * nb32 + (i >> 4));
+    const int li = i & 15;
+    const size_t blk32 = static_cast<size_t>(p * nb32 + (i >> 5));
+    const int il = i & 31, lk = il >> 3, e = il & 7;
+    double r = v;
+#pragma unroll
+    for (int pl = 0; pl < NP; ++pl) {
+      const uint16_t b = bf16_rn_from_double(r);
+      r -= bf16_bits_to_double(b);
+      ta[base + ((blk16 * T8 + a_t) * NP + pl) * 512 + (16 * a_lk + li) * 8 + a_e] = b;
+      tsyn[base + ((blk32 * KR + s_rb) * NP + pl) * 512 + (16 * lk + s_li) * 8 + e] = b;
     }
   };
+  const double x = xs[k];
+  const double sn = ss[k];
+  double pmm = 1.0 / sqrt(4.0 * kPi);
+  for (int i = 1; i <= m; ++i) pmm = -sqrt((2.0 * i + 1.0) / (2.0 * i)) * sn * pmm;
   if (m >= g.lmax) return;
   put(m, pmm);
   if (m + 1 >= g.lmax) return;
@@ -145,28 +212,20 @@ hipError_t launch_grid(int nlat, int kind, double* x, double* s, double* w, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_table(const SegGeom& g, const double* x, const double* s, const int64_t* row_off,
-                        const int* rows_pad, Storage st, void* table, size_t plane_stride,
-                        hipStream_t stream) {
-  const int threads = 64;
-  dim3 grid((g.nk + threads - 1) / threads, g.mmax);
-  switch (st) {
-    case Storage::F32:
-      hipLaunchKernelGGL(table_kernel<0>, grid, dim3(threads), 0, stream, g, x, s, row_off, rows_pad,
-                         table, plane_stride);
-      break;
-    case Storage::BF16:
-      hipLaunchKernelGGL(table_kernel<1>, grid, dim3(threads), 0, stream, g, x, s, row_off, rows_pad,
-                         table, plane_stride);
-      break;
-    case Storage::BF16X2:
-      hipLaunchKernelGGL(table_kernel<2>, grid, dim3(threads), 0, stream, g, x, s, row_off, rows_pad,
-                         table, plane_stride);
-      break;
-    case Storage::BF16X3:
-      hipLaunchKernelGGL(table_kernel<3>, grid, dim3(threads), 0, stream, g, x, s, row_off, rows_pad,
-                         table, plane_stride);
-      break;
+hipError_t launch_frag_table(const SegGeom& g, const double* x, const double* s, const int64_t* off, float* ta,
+                             float* tsyn, hipStream_t stream) {
+  hipLaunchKernelGGL(frag_table_kernel, dim3((g.nk + 63) / 64, g.mmax), dim3(64), 0, stream, g, x, s, off, ta, tsyn);
+  return hipGetLastError();
+}
+
+hipError_t launch_frag_table_bf16(const SegGeom& g, int planes, const double* x, const double* s,
+                                  const int64_t* off, uint16_t* ta, uint16_t* tsyn, hipStream_t stream) {
+  const dim3 grid((g.nk + 63) / 64, g.mmax);
+  switch (planes) {
+    case 1: hipLaunchKernelGGL(frag_table_bf16_kernel<1>, grid, dim3(64), 0, stream, g, x, s, off, ta, tsyn); break;
+    case 2: hipLaunchKernelGGL(frag_table_bf16_kernel<2>, grid, dim3(64), 0, stream, g, x, s, off, ta, tsyn); break;
+    case 3: hipLaunchKernelGGL(frag_table_bf16_kernel<3>, grid, dim3(64), 0, stream, g, x, s, off, ta, tsyn); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -8,9 +8,6 @@
 
 namespace sht {
 
-// Rows of the folded Legendre table are padded per (m, parity) to a multiple
-// of this, so that every row tile of the contraction kernels is full.
-constexpr int kRowPad = 64;
 // Longest ring DFT supported (LDS budget of the DFT kernels).
 constexpr int kMaxNlon = 2048;
 // Most northern rings (incl. the equator) the contraction kernels hold.
@@ -33,13 +30,15 @@ struct SegGeom {
 // ---- grid_table.hip ----------------------------------------------------
 // Nodes x_k, sin t_k and latitude weights w_k (float64, nlat each).
 hipError_t launch_grid(int nlat, int kind, double* x, double* s, double* w, hipStream_t st);
-// Folded float64 recurrence for P^_l^m(x_k), k < nk, written in storage form.
-// row_off[m]: first row of order m; rows_pad[m]: rows per parity block.
-// planes: number of bf16 planes (1 for BF16, 2 for BF16X2, 3 for BF16X3);
-// for F32 `table` holds floats.  Plane stride (elements) = plane_stride.
-hipError_t launch_table(const SegGeom& g, const double* x, const double* s, const int64_t* row_off,
-                        const int* rows_pad, Storage st, void* table, size_t plane_stride,
-                        hipStream_t stream);
+// Legendre table (float64 recurrence, float32 values) in the fragment
+// orders of the analysis (ta) and synthesis (tsyn) kernels; off[m] is the
+// first float of order m in both tables.
+hipError_t launch_frag_table(const SegGeom& g, const double* x, const double* s, const int64_t* off, float* ta,
+                             float* tsyn, hipStream_t stream);
+// The same table as `planes` bf16 planes (hi, [mid,] lo) in the fragment
+// orders of the bf16 kernels; off[m] counts bf16 elements.
+hipError_t launch_frag_table_bf16(const SegGeom& g, int planes, const double* x, const double* s,
+                                  const int64_t* off, uint16_t* ta, uint16_t* tsyn, hipStream_t stream);
 
 // ---- dft.hip -------------------------------------------------------------
 struct DftPlan {
@@ -67,10 +66,9 @@ hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* 
 // {m, 2 * column chunk + ring half}.  ncb = field groups per column chunk.
 struct LegArgs {
   SegGeom g;
-  const void* table;
-  size_t plane_stride;
-  const int64_t* row_off;
-  const int* rows_pad;
+  const void* tab_ana;     // Legendre table, analysis fragment order
+  const void* tab_syn;     // Legendre table, synthesis fragment order
+  const int64_t* tab_off;  // [mmax] first element of order m
   const int2* work;
   int work_per;
   const int2* work_syn;
@@ -81,13 +79,18 @@ struct LegArgs {
 int legendre_ring_pad(int nk);
 // Field groups per column chunk for a segment with `groups` groups.
 int legendre_ncb(int groups);
-// y[f][l][m] = mscale_m sum_k P[m][p][i][k] W[m][p][g][k][..] (l = m + p + 2i),
+// y[f][l][m] = mscale_m sum_k P^_l^m(x_k) W[m][p][g][k][..] (p = (l - m) & 1),
 // mscale_0 = 1, mscale_m = c_rest; y[f][l][m] = 0 for l < m.
 hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y,
                                     float c_rest, hipStream_t stream);
-// W[m][p][g][k][..] = sum_i P[m][p][i][k] y[f][m + p + 2i][m]
+// W[m][p][g][k][..] = sum_{l = m + p + 2i < lmax} P^_l^m(x_k) y[f][l][m]
 hipError_t launch_legendre_synthesis(const LegArgs& a, Storage st, const float2* y, float* W,
                                      hipStream_t stream);
+// bf16 forms (legendre_bf16.hip), same contract with `planes` table planes.
+hipError_t launch_legendre_analysis_bf16(const LegArgs& a, int planes, const float* W, float2* y, float c_rest,
+                                         hipStream_t stream);
+hipError_t launch_legendre_synthesis_bf16(const LegArgs& a, int planes, const float2* y, float* W,
+                                          hipStream_t stream);
 
 // ---- mix.hip -------------------------------------------------------------
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,

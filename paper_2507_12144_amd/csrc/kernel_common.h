@@ -1,0 +1,24 @@
+// Small device helpers shared by the contraction kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sht {
+
+// Work item of this workgroup.  The hardware deals workgroups to the 8 XCDs
+// round-robin (workgroup b runs on XCD b % 8); work lists hold 8 slices of
+// `per` items, one per XCD, so slice x is processed in order on XCD x.
+__device__ __forceinline__ int2 take_work(const int2* __restrict__ work, int per) {
+  const int slot = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  return work[slot];
+}
+
+// Depth of an operand prefetch ring: the largest divisor of the steps per
+// row block that does not exceed `cap`.
+constexpr int ring_depth(int steps, int cap = 8) {
+  for (int d = cap; d > 1; --d)
+    if (steps % d == 0) return d;
+  return 1;
+}
+
+}  // namespace sht

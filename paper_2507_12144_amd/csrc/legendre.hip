@@ -8,94 +8,46 @@
 //   analysis : u^[l] = sum_{k<nk} P^_l^m(x_k) (p == 0 ? S_k : A_k)
 //   synthesis: E_k = sum_{p=0 rows} P^ u^,  O_k = sum_{p=1 rows} P^ u^,
 //              north ring = E + O, mirrored ring = E - O
-// which halves both the table and the multiply-adds.  S, A, E, O live in the
-// workspace W[m][p][g][k][16] (g = group of 8 fields, 16 = their re/im).
+// which halves the multiply-adds.  S, A, E, O live in the workspace
+// W[m][p][g][k][16] (g = group of 8 fields, 16 = their re/im).
 //
-// Work decomposition.  One workgroup per (m, column chunk of NCB groups),
-// 2*NCB waves; wave (p, j) owns parity p and field group c*NCB + j, i.e. one
-// 16-column MFMA block.
+// Streaming design.  The Legendre table is stored in MFMA fragment order
+// (see the table kernel), so every wave streams its own A operands straight
+// from L2 as contiguous 1 KiB loads, several in flight in a register ring,
+// with no LDS staging and no barriers: waves never wait for each other.
+// One workgroup per (m, column chunk of NCB field groups), 2*NCB waves;
+// wave (p, j) owns parity p and field group c*NCB + j (one 16-column MFMA
+// block).  The NCB waves of one parity read the same table lines (L1 hits),
+// the chunks of one m run together on one XCD (L2 hits).
 //  * analysis: the wave keeps its whole K = kpad slice of S or A in VGPRs
-//    (read once from HBM) and streams the table through LDS in 16-row tiles
-//    of both parities; each tile is one 16 x 16 output block per wave.
-//  * synthesis: the wave keeps its whole kpad x 16 output block in VGPRs and
-//    streams table tiles and 16-degree slices of the spectrum through LDS.
+//    (read once from HBM); each 16-row block of its parity is one 16 x 16
+//    output block, written to the spectrum.
+//  * synthesis: the wave keeps its whole kpad x 16 output block in VGPRs;
+//    the spectrum values (B operands) are read one row block ahead.
 // Workgroups are dealt to XCDs in chunks of 16 consecutive m so that each
 // XCD gets a balanced share of the triangle and the 8-byte accesses of
 // neighbouring m to the spectral tensor (m fastest) meet in its L2.
 #include "internal.h"
+#include "kernel_common.h"
 
 namespace sht {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-// native 4-float vector for register staging and 128-bit LDS / global
-// accesses (HIP's float4 is a struct and its copies do not stay in VGPRs)
+// native 4-float vector (HIP's float4 is a struct; its copies do not stay in
+// VGPRs)
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int TR = 16;  // table rows per parity per LDS tile
-
-__device__ __forceinline__ int2 take_work(const int2* __restrict__ work, int per) {
-  const int slot = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  return work[slot];
-}
-
-// One pipeline stage of the table: rows [16 ib, 16 ib + 16) of both parity
-// blocks of order m, restricted to the ring half [h KH, h KH + KH).  It is
-// fetched into registers one stage ahead (4 float4 per thread for the
-// 384-ring grids) and written to an LDS buffer Pt[2][16][KH + 4] after the
-// current stage's MFMAs; the pipeline needs one barrier per stage.
-template <int KPAD, int NTH>
-struct HalfTile {
-  static constexpr int KH = KPAD / 2;
-  static constexpr int Q = KH / 4;  // float4 per half row
-  static constexpr int PITCH = KH + 4;
-  static constexpr int N4 = 2 * TR * Q;
-  static constexpr int PER = (N4 + NTH - 1) / NTH;
-  static constexpr int FULL = N4 / NTH;
-  static constexpr int LDS = 2 * TR * PITCH;  // floats per buffer
-  __device__ static __forceinline__ int goff(int rows_pad, int ib, int h, int e) {
-    const int pp = e / (TR * Q);
-    const int rem = e - pp * TR * Q;
-    const int r = rem / Q;
-    const int q = rem - r * Q;
-    return (pp * rows_pad + TR * ib + r) * KPAD + h * KH + 4 * q;
-  }
-  __device__ static __forceinline__ int loff(int e) {
-    const int pp = e / (TR * Q);
-    const int rem = e - pp * TR * Q;
-    const int r = rem / Q;
-    const int q = rem - r * Q;
-    return (pp * TR + r) * PITCH + 4 * q;
-  }
-};
-// fetch / store of a HalfTile stage through the register array V[PER]
-#define SHT_TILE_FETCH(V, T0, ROWS_PAD, IB, H)                                                      \
-  _Pragma("unroll") for (int u_ = 0; u_ < Tile::PER; ++u_) {                                        \
-    const int e_ = threadIdx.x + u_ * NTH;                                                          \
-    if (u_ < Tile::FULL || e_ < Tile::N4)                                                           \
-      V[u_] = *reinterpret_cast<const v4f*>((T0) + Tile::goff((ROWS_PAD), (IB), (H), e_));          \
-  }
-#define SHT_TILE_STORE(V, PT)                                                                       \
-  _Pragma("unroll") for (int u_ = 0; u_ < Tile::PER; ++u_) {                                        \
-    const int e_ = threadIdx.x + u_ * NTH;                                                          \
-    if (u_ < Tile::FULL || e_ < Tile::N4) *reinterpret_cast<v4f*>((PT) + Tile::loff(e_)) = V[u_];    \
-  }
-
-// Analysis.  A wave's K = KPAD contraction is split into two ring halves of
-// KSH = KS/2 substeps; within half h, substep s' and lane group lk cover ring
-// k = h KH + lk KSH + s', so that one 128-bit LDS read yields the A operands
-// of four consecutive substeps.  Pipeline stages are (16-row tile ib, half h).
+// Analysis.  Contraction index k of a wave's K slice = lk * KS + 4t + q for
+// lane group lk, step t and component q of the 16-byte operand.
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB, 3) void analysis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                                const float* __restrict__ W,
-                                                                float2* __restrict__ y, float c_rest) {
+__global__ __launch_bounds__(128 * NCB) void analysis_kernel(LegArgs a, const int2* __restrict__ work, int per,
+                                                             const float* __restrict__ W, float2* __restrict__ y,
+                                                             float c_rest) {
   constexpr int NTH = 128 * NCB;
   constexpr int KPAD = 4 * KS;
-  constexpr int KSH = KS / 2;
-  using Tile = HalfTile<KPAD, NTH>;
-  constexpr int PITCH = Tile::PITCH;
-  static_assert(KSH % 4 == 0, "KS");
-  __shared__ __attribute__((aligned(16))) float Pt[2 * Tile::LDS];
+  constexpr int T4 = KS / 4;  // 16-byte operand loads per row block
+  constexpr int D = ring_depth(T4);
   const int2 wk = take_work(work, per);
   const int m = wk.x, c = wk.y;
   if (m < 0) return;
@@ -103,62 +55,47 @@ __global__ __launch_bounds__(128 * NCB, 3) void analysis_kernel(LegArgs a, const
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave / NCB, j = wave - p * NCB;
   const int cb = c * NCB + j;
-  const bool active = cb < g.groups;
   const int li = lane & 15, lk = lane >> 4;
-  float xr[KS];
-  if (active) {
-    const float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16;
+  if (cb < g.groups) {
+    float xr[KS];
+    {
+      const float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16 + lk * KS * 16 + li;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int k = (s / KSH) * Tile::KH + lk * KSH + (s % KSH);
-      xr[s] = Wp[k * 16 + li];
+      for (int s = 0; s < KS; ++s) xr[s] = Wp[16 * s];
     }
-  }
-  const int n0 = (g.lmax - m + 1) >> 1;
-  const int np = p ? (g.lmax - m) >> 1 : n0;
-  const int nblk = (n0 + TR - 1) / TR;
-  const int nst = 2 * nblk;
-  const float* T0 = static_cast<const float*>(a.table) + static_cast<size_t>(a.row_off[m]) * KPAD;
-  const int rows_pad = a.rows_pad[m];
-  const float ms = (m == 0) ? 1.f : c_rest;
-  float* yf = reinterpret_cast<float*>(y);
-  const int f = 8 * cb + (li >> 1);
-  v4f tv[Tile::PER];
-  SHT_TILE_FETCH(tv, T0, rows_pad, 0, 0);
-  SHT_TILE_STORE(tv, Pt);
-  __syncthreads();
-  SHT_TILE_FETCH(tv, T0, rows_pad, 0, 1);
-  const bool work_rows = active;
-  for (int ib = 0; ib < nblk; ++ib) {
-    const bool mine = work_rows && TR * ib < np;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int n0 = (g.lmax - m + 1) >> 1;
+    const int nb = (n0 + 15) >> 4;
+    const int np = p ? (g.lmax - m) >> 1 : n0;
+    const int nbp = (np + 15) >> 4;
+    const int last = nbp > 0 ? nbp * T4 - 1 : 0;  // clamp: prefetches never leave the table
+    const v4f* A = reinterpret_cast<const v4f*>(static_cast<const float*>(a.tab_ana) + a.tab_off[m]) + static_cast<size_t>(p * nb) * T4 * 64 + lane;
+    const float ms = (m == 0) ? 1.f : c_rest;
+    float* yf = reinterpret_cast<float*>(y);
+    const int f = 8 * cb + (li >> 1);
+    const bool fok = f < g.F;
+    v4f ring[D];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int st = 2 * ib + h;
-      if (mine) {
-        const v4f* Pr = reinterpret_cast<const v4f*>(Pt + h * Tile::LDS + (p * TR + li) * PITCH + lk * KSH);
-        v4f cur = Pr[0];
+    for (int u = 0; u < D; ++u) ring[u] = A[static_cast<size_t>(min(u, last)) * 64];
+    for (int ib = 0; ib < nbp; ++ib) {
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < KSH / 4; ++t) {
-          const v4f nxt = (t + 1 < KSH / 4) ? Pr[t + 1] : cur;
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.x, xr[h * KSH + 4 * t + 0], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.y, xr[h * KSH + 4 * t + 1], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.z, xr[h * KSH + 4 * t + 2], acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.w, xr[h * KSH + 4 * t + 3], acc, 0, 0, 0);
-          cur = nxt;
-        }
+      for (int t = 0; t < T4; ++t) {
+        const v4f av = ring[t % D];
+        const int q = ib * T4 + t + D;
+        ring[t % D] = A[static_cast<size_t>(min(q, last)) * 64];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xr[4 * t + 0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xr[4 * t + 1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xr[4 * t + 2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[4 * t + 3], acc, 0, 0, 0);
       }
-      if (st + 1 < nst) SHT_TILE_STORE(tv, Pt + (1 - h) * Tile::LDS);
-      __syncthreads();
-      if (st + 2 < nst) SHT_TILE_FETCH(tv, T0, rows_pad, ib + 1, h);
-    }
-    if (mine && f < g.F) {
+      if (fok) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = TR * ib + 4 * lk + r;
-        if (i < np) {
-          const int l = m + p + 2 * i;
-          yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = acc[r] * ms;
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * ib + 4 * lk + r;
+          if (i < np) {
+            const int l = m + p + 2 * i;
+            yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = acc[r] * ms;
+          }
         }
       }
     }
@@ -174,137 +111,85 @@ __global__ __launch_bounds__(128 * NCB, 3) void analysis_kernel(LegArgs a, const
   }
 }
 
-// Synthesis.  A workgroup owns ring half kh of order m for one column chunk;
-// output ring k = kh KH + i KR + rb of a wave's block (MFMA row i, row block
-// rb) so that one 128-bit LDS read yields the A operands of four consecutive
-// row blocks.  Pipeline stages are 16-degree tiles of both parities.
+// Synthesis.  Output ring k of a wave's block = li * KR + 4t + q for MFMA row
+// li, step t and component q; contraction row i = 16 ib + 4 s + lk.
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB, 3) void synthesis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                                 const float2* __restrict__ y,
-                                                                 float* __restrict__ W) {
-  constexpr int NTH = 128 * NCB;
+__global__ __launch_bounds__(128 * NCB) void synthesis_kernel(LegArgs a, const int2* __restrict__ work, int per,
+                                                              const float2* __restrict__ y, float* __restrict__ W) {
   constexpr int KPAD = 4 * KS;
-  using Tile = HalfTile<KPAD, NTH>;
-  constexpr int KH = Tile::KH;
-  constexpr int KR = KH / 16;  // 16-ring output blocks of the half
+  constexpr int KR = KPAD / 16;  // 16-ring output blocks
+  constexpr int T4 = KR / 4;     // 16-byte operand loads per substep
+  constexpr int STEPS = 4 * T4;  // operand loads per row block
+  constexpr int D = ring_depth(STEPS);
   static_assert(KR % 4 == 0, "KR");
-  constexpr int PITCH = Tile::PITCH;
-  constexpr int NF = 8 * NCB;       // fields of the chunk
-  constexpr int BPITCH = 2 * NF + 4;
-  constexpr int BLDS = 2 * TR * BPITCH;
-  constexpr int NB = 2 * TR * NF;   // spectral values per stage
-  constexpr int BPER = (NB + NTH - 1) / NTH;
-  __shared__ __attribute__((aligned(16))) float Pt[2 * Tile::LDS];
-  __shared__ __attribute__((aligned(16))) float Bt[2 * BLDS];
   const int2 wk = take_work(work, per);
-  const int m = wk.x;
+  const int m = wk.x, c = wk.y;
   if (m < 0) return;
-  const int c = wk.y >> 1, kh = wk.y & 1;
   const SegGeom& g = a.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave / NCB, j = wave - p * NCB;
   const int cb = c * NCB + j;
-  const bool active = cb < g.groups;
-  const int n0 = (g.lmax - m + 1) >> 1;
-  const int n1 = (g.lmax - m) >> 1;
-  const int np = p ? n1 : n0;
-  const int nblk = (n0 + TR - 1) / TR;
-  const float* T0 = static_cast<const float*>(a.table) + static_cast<size_t>(a.row_off[m]) * KPAD;
-  const int rows_pad = a.rows_pad[m];
+  if (cb >= g.groups) return;
   const int li = lane & 15, lk = lane >> 4;
-  const int fbeg = NF * c;
-  // 16 degrees of each parity x this chunk's fields, gathered from the
-  // spectral tensor (m fastest)
-  float2 bv_reg[BPER];
-#define SHT_FETCH_B(IB)                                                                       \
-  _Pragma("unroll") for (int u = 0; u < BPER; ++u) {                                          \
-    const int e = threadIdx.x + u * NTH;                                                      \
-    float2 v = make_float2(0.f, 0.f);                                                         \
-    if (e < NB) {                                                                             \
-      const int pp = e / (TR * NF);                                                           \
-      const int rem = e - pp * TR * NF;                                                       \
-      const int r = rem / NF;                                                                 \
-      const int fl = rem - r * NF;                                                            \
-      const int i = TR * (IB) + r;                                                            \
-      const int ff = fbeg + fl;                                                               \
-      if (i < (pp ? n1 : n0) && ff < g.F)                                                     \
-        v = y[(static_cast<size_t>(ff) * g.lmax + m + pp + 2 * i) * g.mmax + m];              \
-    }                                                                                         \
-    bv_reg[u] = v;                                                                            \
-  }
-#define SHT_STORE_B(B)                                                                        \
-  _Pragma("unroll") for (int u = 0; u < BPER; ++u) {                                          \
-    const int e = threadIdx.x + u * NTH;                                                      \
-    if (e < NB) {                                                                             \
-      const int pp = e / (TR * NF);                                                           \
-      const int rem = e - pp * TR * NF;                                                       \
-      const int r = rem / NF;                                                                 \
-      const int fl = rem - r * NF;                                                            \
-      *reinterpret_cast<float2*>((B) + (pp * TR + r) * BPITCH + 2 * fl) = bv_reg[u];          \
-    }                                                                                         \
-  }
+  const int n0 = (g.lmax - m + 1) >> 1;
+  const int nb = (n0 + 15) >> 4;
+  const int np = p ? (g.lmax - m) >> 1 : n0;
+  const int nbp = (np + 15) >> 4;
+  const int last = nbp > 0 ? nbp * STEPS - 1 : 0;  // clamp: prefetches never leave the table
+  const v4f* A = reinterpret_cast<const v4f*>(static_cast<const float*>(a.tab_syn) + a.tab_off[m]) + static_cast<size_t>(p * nb) * STEPS * 64 + lane;
+  // B operand of lane (li, lk) at substep s of row block ib: re (li even) or
+  // im (li odd) of field 8 cb + li/2 at degree l = m + p + 2 (16 ib + 4 s + lk)
+  const float* yf = reinterpret_cast<const float*>(y);
+  const int f = 8 * cb + (li >> 1);
+  const bool fok = f < g.F;
+  const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
+  auto bload = [&](int ib, int s) {
+    const int i = 16 * ib + 4 * s + lk;
+    const bool ok = fok && i < np;
+    const int l = ok ? m + p + 2 * i : m;
+    const float v = yf[(fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1)];
+    return ok ? v : 0.f;
+  };
   floatx4 acc[KR];
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  v4f tv[Tile::PER];
-  SHT_TILE_FETCH(tv, T0, rows_pad, 0, kh);
-  SHT_FETCH_B(0);
-  SHT_TILE_STORE(tv, Pt);
-  SHT_STORE_B(Bt);
-  __syncthreads();
-  if (nblk > 1) {
-    SHT_TILE_FETCH(tv, T0, rows_pad, 1, kh);
-    SHT_FETCH_B(1);
-  }
-  constexpr int NQ = 4 * (KR / 4);
-  for (int ib = 0; ib < nblk; ++ib) {
-    const float* Pb = Pt + (ib & 1) * Tile::LDS;
-    const float* Bb = Bt + (ib & 1) * BLDS;
-    if (active && TR * ib < np) {
-      // flattened schedule q = (substep s, 4-block group t): one 128-bit A
-      // read and four MFMAs per step, A reads issued two steps ahead
-      const float* Pbase = Pb + (p * TR + lk) * PITCH + li * KR;
-      float bvs[4];
+  v4f ring[D];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) bvs[s] = Bb[(p * TR + 4 * s + lk) * BPITCH + 16 * j + li];
-      v4f ring[3];
-      ring[0] = reinterpret_cast<const v4f*>(Pbase)[0];
-      ring[1] = reinterpret_cast<const v4f*>(Pbase + 4 * (1 / (KR / 4)) * PITCH)[1 % (KR / 4)];
+  for (int u = 0; u < D; ++u) ring[u] = A[static_cast<size_t>(min(u, last)) * 64];
+  float bn[4];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (q + 2 < NQ) {
-          const int s2 = (q + 2) / (KR / 4), t2 = (q + 2) - s2 * (KR / 4);
-          ring[(q + 2) % 3] = reinterpret_cast<const v4f*>(Pbase + 4 * s2 * PITCH)[t2];
-        }
-        const int s = q / (KR / 4), t = q - s * (KR / 4);
-        const v4f av = ring[q % 3];
-        acc[4 * t + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bvs[s], acc[4 * t + 0], 0, 0, 0);
-        acc[4 * t + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bvs[s], acc[4 * t + 1], 0, 0, 0);
-        acc[4 * t + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bvs[s], acc[4 * t + 2], 0, 0, 0);
-        acc[4 * t + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bvs[s], acc[4 * t + 3], 0, 0, 0);
+  for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
+  for (int ib = 0; ib < nbp; ++ib) {
+    float bc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) bc[s] = bn[s];
+    if (ib + 1 < nbp) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bn[s] = bload(ib + 1, s);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int t = 0; t < T4; ++t) {
+        const int st = s * T4 + t;
+        const v4f av = ring[st % D];
+        const int q = ib * STEPS + st + D;
+        ring[st % D] = A[static_cast<size_t>(min(q, last)) * 64];
+        acc[4 * t + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bc[s], acc[4 * t + 0], 0, 0, 0);
+        acc[4 * t + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bc[s], acc[4 * t + 1], 0, 0, 0);
+        acc[4 * t + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bc[s], acc[4 * t + 2], 0, 0, 0);
+        acc[4 * t + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bc[s], acc[4 * t + 3], 0, 0, 0);
       }
     }
-    if (ib + 1 < nblk) {
-      SHT_TILE_STORE(tv, Pt + ((ib + 1) & 1) * Tile::LDS);
-      SHT_STORE_B(Bt + ((ib + 1) & 1) * BLDS);
-    }
-    __syncthreads();
-    if (ib + 2 < nblk) {
-      SHT_TILE_FETCH(tv, T0, rows_pad, ib + 2, kh);
-      SHT_FETCH_B(ib + 2);
-    }
   }
-#undef SHT_FETCH_B
-#undef SHT_STORE_B
-#undef SHT_TILE_FETCH
-#undef SHT_TILE_STORE
-  if (active) {
-    float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16 + static_cast<size_t>(kh) * KH * 16;
+  float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16;
+  // acc[4t + q][r] is output row 4 lk + r, ring k = (4 lk + r) * KR + 4 t + q
 #pragma unroll
-    for (int rb = 0; rb < KR; ++rb)
+  for (int t = 0; t < T4; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Wp[((4 * lk + r) * KR + rb) * 16 + li] = acc[rb][r];
-  }
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wp[((4 * lk + r) * KR + 4 * t + q) * 16 + li] = acc[4 * t + q][r];
 }
 
 template <int NCB, int KS>
@@ -324,7 +209,9 @@ hipError_t launch_pair(bool analysis, const LegArgs& a, const void* in, void* ou
 template <int NCB>
 hipError_t by_ks(bool analysis, const LegArgs& a, const void* in, void* out, float c_rest, hipStream_t st) {
   switch (a.g.kpad / 4) {
+    case 16: return launch_pair<NCB, 16>(analysis, a, in, out, c_rest, st);
     case 32: return launch_pair<NCB, 32>(analysis, a, in, out, c_rest, st);
+    case 48: return launch_pair<NCB, 48>(analysis, a, in, out, c_rest, st);
     case 64: return launch_pair<NCB, 64>(analysis, a, in, out, c_rest, st);
     case 96: return launch_pair<NCB, 96>(analysis, a, in, out, c_rest, st);
     default: return hipErrorInvalidValue;
@@ -345,7 +232,7 @@ hipError_t dispatch(bool analysis, const LegArgs& a, Storage st, const void* in,
 }  // namespace
 
 int legendre_ring_pad(int nk) {
-  const int ks[] = {32, 64, 96};
+  const int ks[] = {16, 32, 48, 64, 96};
   for (int k : ks)
     if (4 * k >= nk) return 4 * k;
   return -1;

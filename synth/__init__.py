@@ -19,13 +19,16 @@ import numpy as np
 def coefficients(seed, batch, channels, lmax, mmax):
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((batch, channels, lmax, mmax, 2))
-    a = z[..., 0] + 1j * z[..., 1]
+    a = np.empty((batch, channels, lmax, mmax), dtype=np.complex128)
+    a.real = z[..., 0]
+    a.imag = z[..., 1]
+    del z
     scale = 1.0 / (np.arange(lmax, dtype=np.float64) + 1.0)
-    a = a * scale[None, None, :, None]
-    a[..., 0] = a[..., 0].real
+    a *= scale[None, None, :, None]
+    a[..., 0].imag = 0.0
     l = np.arange(lmax)[:, None]
     m = np.arange(mmax)[None, :]
-    a = np.where((l >= m)[None, None], a, 0.0)
+    a *= (l >= m)
     return a
 
 
