@@ -97,8 +97,6 @@ struct Segment {
   int64_t* tab_off = nullptr;  // [mmax]
   int2* worklist = nullptr;
   int work_per = 0;
-  int2* worklist_syn = nullptr;
-  int work_syn_per = 0;
   int ncb = 1;
   float* work = nullptr;
 };
@@ -151,7 +149,7 @@ namespace {
 
 void free_segment(Segment& s) {
   void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.tab_ana, s.tab_syn, s.tab_off,
-                  s.worklist, s.worklist_syn, s.work};
+                  s.worklist, s.work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = Segment{};
@@ -245,15 +243,33 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
     if (e != hipSuccess) return hip_fail(e, "Legendre table kernel");
   }
 
-  // contraction work list: chunks of 16 consecutive m dealt round-robin to
-  // the 8 XCDs, each XCD's chunks in ascending m (largest work first)
-  for (int syn = 0; syn < 2; ++syn) {
+  // contraction work list: the orders come in chunks of 16 consecutive m
+  // (whose 8-byte spectrum entries share 128-byte lines); chunks go to the 8
+  // XCDs largest first, each to the XCD with the least work so far, and each
+  // XCD processes its chunks in ascending m (largest items first).  The
+  // work of an item is taken as its number of 16-row blocks plus one.
+  {
     const int chunks_per_m = (g.groups + S.ncb - 1) / S.ncb;
-    const int sub = syn ? 2 : 1;  // the synthesis splits the rings in two halves
+    const int nq = (d.mmax + 15) / 16;
+    std::vector<int64_t> qwork(nq, 0);
+    for (int m = 0; m < d.mmax; ++m) qwork[m / 16] += static_cast<int64_t>(chunks_per_m) * ((((d.lmax - m + 1) >> 1) + 15) / 16 + 1);
+    std::vector<int> order(nq);
+    for (int q = 0; q < nq; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return qwork[x] > qwork[y]; });
+    std::vector<std::vector<int>> xq(8);
+    std::vector<int64_t> load(8, 0);
+    for (int q : order) {
+      const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      xq[x].push_back(q);
+      load[x] += qwork[q];
+    }
     std::vector<std::vector<int2>> slices(8);
-    for (int q = 0; q * 16 < d.mmax; ++q)
-      for (int m = 16 * q; m < std::min(d.mmax, 16 * q + 16); ++m)
-        for (int c = 0; c < chunks_per_m * sub; ++c) slices[q % 8].push_back(make_int2(m, c));
+    for (int x = 0; x < 8; ++x) {
+      std::sort(xq[x].begin(), xq[x].end());
+      for (int q : xq[x])
+        for (int m = 16 * q; m < std::min(d.mmax, 16 * q + 16); ++m)
+          for (int c = 0; c < chunks_per_m; ++c) slices[x].push_back(make_int2(m, c));
+    }
     size_t per = 1;
     for (auto& v : slices) per = std::max(per, v.size());
     std::vector<int2> flat;
@@ -262,13 +278,8 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
       v.resize(per, make_int2(-1, -1));
       flat.insert(flat.end(), v.begin(), v.end());
     }
-    if (syn) {
-      S.work_syn_per = static_cast<int>(per);
-      if ((rc = upload(&S.worklist_syn, flat, st, "work list")) != SHT_OK) return rc;
-    } else {
-      S.work_per = static_cast<int>(per);
-      if ((rc = upload(&S.worklist, flat, st, "work list")) != SHT_OK) return rc;
-    }
+    S.work_per = static_cast<int>(per);
+    if ((rc = upload(&S.worklist, flat, st, "work list")) != SHT_OK) return rc;
   }
 
   // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
@@ -290,8 +301,6 @@ LegArgs leg_args(const Segment& S) {
   a.tab_off = S.tab_off;
   a.work = S.worklist;
   a.work_per = S.work_per;
-  a.work_syn = S.worklist_syn;
-  a.work_syn_per = S.work_syn_per;
   a.ncb = S.ncb;
   return a;
 }

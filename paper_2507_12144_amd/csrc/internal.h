@@ -62,8 +62,8 @@ hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* 
 
 // ---- legendre.hip --------------------------------------------------------
 // Work lists: 8 slices (one per XCD) of work_per entries, padded with
-// {-1, -1}; analysis items are {m, column chunk}, synthesis items
-// {m, 2 * column chunk + ring half}.  ncb = field groups per column chunk.
+// {-1, -1}; items are {m, column chunk}.  ncb = field groups per column
+// chunk.
 struct LegArgs {
   SegGeom g;
   const void* tab_ana;     // Legendre table, analysis fragment order
@@ -71,8 +71,6 @@ struct LegArgs {
   const int64_t* tab_off;  // [mmax] first element of order m
   const int2* work;
   int work_per;
-  const int2* work_syn;
-  int work_syn_per;
   int ncb;
 };
 // Ring padding the contraction kernels support for nk rings (-1: none).

@@ -22,3 +22,23 @@ constexpr int ring_depth(int steps, int cap = 8) {
 }
 
 }  // namespace sht
+
+namespace sht {
+
+// s_waitcnt immediate that waits until at most n vector-memory operations of
+// this wave are outstanding (expcnt and lgkmcnt left at their maxima).
+constexpr int vm_wait(int n) { return 0x0F70 | (n & 15) | (((n >> 4) & 3) << 14); }
+
+// Workgroup barrier for LDS filled by asynchronous global->LDS copies.  The
+// caller first waits (vm_wait) for its own copies of the stage; the barrier
+// then makes every wave's copies visible.  The empty asm statements keep the
+// compiler from moving memory operations across the barrier; unlike
+// __syncthreads() no fence is emitted, so copies of later stages stay in
+// flight.
+__device__ __forceinline__ void stage_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+}  // namespace sht

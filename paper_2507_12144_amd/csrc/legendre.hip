@@ -11,22 +11,28 @@
 // which halves the multiply-adds.  S, A, E, O live in the workspace
 // W[m][p][g][k][16] (g = group of 8 fields, 16 = their re/im).
 //
-// Streaming design.  The Legendre table is stored in MFMA fragment order
-// (see the table kernel), so every wave streams its own A operands straight
-// from L2 as contiguous 1 KiB loads, several in flight in a register ring,
-// with no LDS staging and no barriers: waves never wait for each other.
-// One workgroup per (m, column chunk of NCB field groups), 2*NCB waves;
-// wave (p, j) owns parity p and field group c*NCB + j (one 16-column MFMA
-// block).  The NCB waves of one parity read the same table lines (L1 hits),
-// the chunks of one m run together on one XCD (L2 hits).
+// Pipelined design.  The Legendre table is stored in MFMA fragment order
+// (see the table kernel): a wave's A operands of four consecutive MFMA steps
+// are one contiguous 1 KiB piece, 16 bytes a lane.  One workgroup per (m,
+// column chunk of NCB field groups) has 2*NCB waves; wave (p, j) owns parity
+// p and field group c*NCB + j (one 16-column MFMA block).  The table is
+// consumed in stages of a half or a third of a 16-row block for both
+// parities that pass through a ring of three LDS buffers, filled by
+// asynchronous global->LDS copies (global_load_lds_dwordx4) that the waves
+// share out: while the waves multiply stage s, the copies of stages s+1 and
+// s+2 are in flight, and no operand passes through VGPRs on its way to LDS.
+// The NCB waves of one parity read each piece from LDS.
 //  * analysis: the wave keeps its whole K = kpad slice of S or A in VGPRs
 //    (read once from HBM); each 16-row block of its parity is one 16 x 16
 //    output block, written to the spectrum.
 //  * synthesis: the wave keeps its whole kpad x 16 output block in VGPRs;
 //    the spectrum values (B operands) are read one row block ahead.
-// Workgroups are dealt to XCDs in chunks of 16 consecutive m so that each
-// XCD gets a balanced share of the triangle and the 8-byte accesses of
-// neighbouring m to the spectral tensor (m fastest) meet in its L2.
+// Occupancy.  At kpad = 384 a wave needs about 160 VGPRs, so a SIMD holds
+// three.  Workgroups of four waves (NCB = 2) put one wave on each SIMD, so
+// three workgroups share a CU (3 x 48 KiB of LDS); a workgroup of six waves
+// would take two wave slots on every SIMD and leave room for no second one.
+#include <type_traits>
+
 #include "internal.h"
 #include "kernel_common.h"
 
@@ -38,90 +44,73 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // VGPRs)
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Analysis.  Contraction index k of a wave's K slice = lk * KS + 4t + q for
-// lane group lk, step t and component q of the 16-byte operand.
+// Stage geometry shared by both kernels.  A row block and parity hold T4
+// pieces of 1 KiB; a stage takes SC = T4 / PARTS of them for each parity.
+// The 2*NCB waves issue LPW copies each per stage (the last piece is
+// repeated when 2*SC is not a multiple of the wave count: identical bytes).
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB) void analysis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                             const float* __restrict__ W, float2* __restrict__ y,
-                                                             float c_rest) {
-  constexpr int NTH = 128 * NCB;
-  constexpr int KPAD = 4 * KS;
-  constexpr int T4 = KS / 4;  // 16-byte operand loads per row block
-  constexpr int D = ring_depth(T4);
-  const int2 wk = take_work(work, per);
-  const int m = wk.x, c = wk.y;
-  if (m < 0) return;
-  const SegGeom& g = a.g;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int p = wave / NCB, j = wave - p * NCB;
-  const int cb = c * NCB + j;
-  const int li = lane & 15, lk = lane >> 4;
-  if (cb < g.groups) {
-    float xr[KS];
-    {
-      const float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16 + lk * KS * 16 + li;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) xr[s] = Wp[16 * s];
-    }
-    const int n0 = (g.lmax - m + 1) >> 1;
-    const int nb = (n0 + 15) >> 4;
-    const int np = p ? (g.lmax - m) >> 1 : n0;
-    const int nbp = (np + 15) >> 4;
-    const int last = nbp > 0 ? nbp * T4 - 1 : 0;  // clamp: prefetches never leave the table
-    const v4f* A = reinterpret_cast<const v4f*>(static_cast<const float*>(a.tab_ana) + a.tab_off[m]) + static_cast<size_t>(p * nb) * T4 * 64 + lane;
-    const float ms = (m == 0) ? 1.f : c_rest;
-    float* yf = reinterpret_cast<float*>(y);
-    const int f = 8 * cb + (li >> 1);
-    const bool fok = f < g.F;
-    v4f ring[D];
-#pragma unroll
-    for (int u = 0; u < D; ++u) ring[u] = A[static_cast<size_t>(min(u, last)) * 64];
-    for (int ib = 0; ib < nbp; ++ib) {
-      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < T4; ++t) {
-        const v4f av = ring[t % D];
-        const int q = ib * T4 + t + D;
-        ring[t % D] = A[static_cast<size_t>(min(q, last)) * 64];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xr[4 * t + 0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xr[4 * t + 1], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xr[4 * t + 2], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[4 * t + 3], acc, 0, 0, 0);
-      }
-      if (fok) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * ib + 4 * lk + r;
-          if (i < np) {
-            const int l = m + p + 2 * i;
-            yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = acc[r] * ms;
-          }
-        }
-      }
-    }
+struct Stages {
+  static constexpr int T4 = KS / 4;
+  static constexpr int PARTS = (T4 % 3 == 0) ? 3 : 2;
+  static constexpr int SC = T4 / PARTS;
+  static constexpr int NW = 2 * NCB;
+  static constexpr int LPW = (2 * SC + NW - 1) / NW;
+  static constexpr int NTH = 64 * NW;
+  // stages unrolled into straight-line code: enough for lmax <= 2 kpad, a
+  // multiple of the period after which buffer (stage % 3) and part repeat;
+  // larger lmax goes round an outer loop.  Straight-line code lets the
+  // compiler prove which buffer each copy writes, so it adds no waits of its
+  // own beyond the ones written here.
+  static constexpr int PERIOD = PARTS == 3 ? 3 : 6;
+  static constexpr int NST = ((PARTS * T4 + PERIOD - 1) / PERIOD) * PERIOD;
+};
+
+// Calls f(integral_constant<U>) for U = 0, 1, ..., END-1 as straight-line
+// code, stopping after the first call that returns false.
+template <int U, int END, class F>
+__device__ __forceinline__ bool unrolled(F&& f) {
+  if constexpr (U < END) {
+    if (!f(std::integral_constant<int, U>{})) return false;
+    return unrolled<U + 1, END>(f);
   }
-  // the entries l < m of this chunk's fields are zero
-  const int fbeg = 8 * NCB * c;
-  const int fend = min(g.F, fbeg + 8 * NCB);
-  const int nf = fend - fbeg;
-  for (int e = threadIdx.x; e < m * nf; e += NTH) {
-    const int l = e / nf;
-    const int ff = fbeg + (e - l * nf);
-    y[(static_cast<size_t>(ff) * g.lmax + l) * g.mmax + m] = make_float2(0.f, 0.f);
+  return true;
+}
+
+// LDS buffer of stage u of the ring of three.
+template <int U>
+__device__ __forceinline__ v4f* ring_buf(v4f* b0, v4f* b1, v4f* b2) {
+  if constexpr (U % 3 == 0) return b0;
+  else if constexpr (U % 3 == 1) return b1;
+  else return b2;
+}
+
+// Copy stage st (row block st / PARTS, part st % PARTS) of both parity
+// tables into LDS buffer B.  Stages past the last row block re-read the
+// last one (into a buffer that is never read).
+template <int SC, int NW, int LPW, int PARTS, int T4>
+__device__ __forceinline__ void issue_stage(v4f* B, const float* __restrict__ tab, int nb, int st, int wave,
+                                            int lane) {
+  const int ib = min(st / PARTS, nb - 1), h = st - (st / PARTS) * PARTS;
+#pragma unroll
+  for (int i = 0; i < LPW; ++i) {
+    const int e = min(wave + i * NW, 2 * SC - 1);
+    const int pp = e >= SC ? 1 : 0;
+    const int t = e - pp * SC;
+    const float* src = tab + (static_cast<size_t>(pp * nb + ib) * T4 + h * SC + t) * 256 + lane * 4;
+    __builtin_amdgcn_global_load_lds(src, B + (pp * SC + t) * 64, 16, 0, 0);
   }
 }
 
-// Synthesis.  Output ring k of a wave's block = li * KR + 4t + q for MFMA row
-// li, step t and component q; contraction row i = 16 ib + 4 s + lk.
+// Analysis.  Contraction index k of a wave's K slice = lk * KS + 4t + q for
+// lane group lk, piece t of the row block and component q.
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB) void synthesis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                              const float2* __restrict__ y, float* __restrict__ W) {
+__global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void analysis_kernel(LegArgs a, const int2* __restrict__ work, int per,
+                                                             const float* __restrict__ W, float2* __restrict__ y,
+                                                             float c_rest) {
+  using S = Stages<NCB, KS>;
+  constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, NTH = S::NTH, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
-  constexpr int KR = KPAD / 16;  // 16-ring output blocks
-  constexpr int T4 = KR / 4;     // 16-byte operand loads per substep
-  constexpr int STEPS = 4 * T4;  // operand loads per row block
-  constexpr int D = ring_depth(STEPS);
-  static_assert(KR % 4 == 0, "KR");
+  __shared__ v4f b0[2 * SC * 64], b1[2 * SC * 64], b2[2 * SC * 64];
   const int2 wk = take_work(work, per);
   const int m = wk.x, c = wk.y;
   if (m < 0) return;
@@ -129,63 +118,204 @@ __global__ __launch_bounds__(128 * NCB) void synthesis_kernel(LegArgs a, const i
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave / NCB, j = wave - p * NCB;
   const int cb = c * NCB + j;
-  if (cb >= g.groups) return;
+  const bool active = cb < g.groups;
   const int li = lane & 15, lk = lane >> 4;
   const int n0 = (g.lmax - m + 1) >> 1;
   const int nb = (n0 + 15) >> 4;
   const int np = p ? (g.lmax - m) >> 1 : n0;
   const int nbp = (np + 15) >> 4;
-  const int last = nbp > 0 ? nbp * STEPS - 1 : 0;  // clamp: prefetches never leave the table
-  const v4f* A = reinterpret_cast<const v4f*>(static_cast<const float*>(a.tab_syn) + a.tab_off[m]) + static_cast<size_t>(p * nb) * STEPS * 64 + lane;
+  const int nst = PARTS * nb;
+  const float* tab = static_cast<const float*>(a.tab_ana) + a.tab_off[m];
+  float xr[KS];
+  {
+    // idle waves (past the last field group) load group 0 and never use it
+    const float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + (active ? cb : 0)) * KPAD * 16 + lk * KS * 16 + li;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) xr[s] = Wp[16 * s];
+  }
+  const float ms = (m == 0) ? 1.f : c_rest;
+  float* yf = reinterpret_cast<float*>(y);
+  const int f = 8 * cb + (li >> 1);
+  const bool fok = active && f < g.F;
+  if (nb > 0) {
+    // Every stage issues the copies of stage s+2, past the end too, so that
+    // each wave always has exactly LPW copies in flight behind the ones it
+    // waits for and every wait is the same vm_wait(LPW).
+    issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
+    issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int st0 = 0; st0 < nst; st0 += S::NST) {
+      unrolled<0, S::NST>([&](auto su_c) {
+        constexpr int su = decltype(su_c)::value;
+        constexpr int part = su % PARTS;
+        const int st = st0 + su;
+        if (st >= nst) return false;
+        v4f* cur = ring_buf<su>(b0, b1, b2);
+        v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
+        __builtin_amdgcn_s_waitcnt(vm_wait(LPW));
+        stage_barrier();
+        issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
+        const int ib = st / PARTS;
+        if (active && ib < nbp) {
+#pragma unroll
+          for (int t = 0; t < SC; ++t) {
+            const v4f av = cur[(p * SC + t) * 64 + lane];
+            constexpr int kb = 4 * part * SC;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, xr[kb + 4 * t + 0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, xr[kb + 4 * t + 1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, xr[kb + 4 * t + 2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[kb + 4 * t + 3], acc, 0, 0, 0);
+          }
+          if constexpr (part == PARTS - 1) {
+            if (fok) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = 16 * ib + 4 * lk + r;
+                if (i < np) {
+                  const int l = m + p + 2 * i;
+                  yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = acc[r] * ms;
+                }
+              }
+            }
+            acc = floatx4{0.f, 0.f, 0.f, 0.f};
+          }
+        }
+        return true;
+      });
+    }
+    // no copy may still be writing this workgroup's LDS when it ends
+    __builtin_amdgcn_s_waitcnt(vm_wait(0));
+  }
+  // Zeros of the spectrum (entries l < m'): this workgroup writes those of
+  // degree l = m for its fields, y[f][m][m+1 .. mmax-1], one contiguous run
+  // per field, instead of the scattered column y[f][0 .. m-1][m].
+  if (m < g.lmax) {
+    const int fbeg = 8 * NCB * c;
+    const int fend = min(g.F, fbeg + 8 * NCB);
+    const int run = g.mmax - 1 - m;
+    for (int ff = fbeg; ff < fend; ++ff) {
+      float2* row = y + (static_cast<size_t>(ff) * g.lmax + m) * g.mmax + m + 1;
+      for (int e = threadIdx.x; e < run; e += NTH) row[e] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// Synthesis.  Output ring k of a wave's block = li * KR + 4t + q for MFMA row
+// li, piece t of a substep and component q; contraction row i = 16 ib + 4 s
+// + lk.  Piece e of a row block is substep e / (KR/4), piece e % (KR/4).
+template <int NCB, int KS>
+__global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void synthesis_kernel(LegArgs a, const int2* __restrict__ work, int per,
+                                                              const float2* __restrict__ y, float* __restrict__ W) {
+  using S = Stages<NCB, KS>;
+  constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, PARTS = S::PARTS, T4 = S::T4;
+  constexpr int KPAD = 4 * KS;
+  constexpr int KR = KPAD / 16;  // 16-ring output blocks
+  constexpr int TS = KR / 4;     // pieces per substep
+  static_assert(KR % 4 == 0 && 4 * TS == T4, "stage geometry");
+  __shared__ v4f b0[2 * SC * 64], b1[2 * SC * 64], b2[2 * SC * 64];
+  const int2 wk = take_work(work, per);
+  const int m = wk.x, c = wk.y;
+  if (m < 0) return;
+  const SegGeom& g = a.g;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = wave / NCB, j = wave - p * NCB;
+  const int cb = c * NCB + j;
+  const bool active = cb < g.groups;
+  const int li = lane & 15, lk = lane >> 4;
+  const int n0 = (g.lmax - m + 1) >> 1;
+  const int nb = (n0 + 15) >> 4;
+  const int np = p ? (g.lmax - m) >> 1 : n0;
+  const int nbp = (np + 15) >> 4;
+  const int nst = PARTS * nb;
+  const float* tab = static_cast<const float*>(a.tab_syn) + a.tab_off[m];
   // B operand of lane (li, lk) at substep s of row block ib: re (li even) or
-  // im (li odd) of field 8 cb + li/2 at degree l = m + p + 2 (16 ib + 4 s + lk)
+  // im (li odd) of field 8 cb + li/2 at degree l = m + p + 2 (16 ib + 4 s + lk).
+  // Rows past the parity's last degree read degree m instead: their table
+  // rows are zero, so they add nothing (the value is finite whenever the
+  // field's own values are).  Lanes of fields past F read field 0; those
+  // columns of the workspace are never read back.
   const float* yf = reinterpret_cast<const float*>(y);
   const int f = 8 * cb + (li >> 1);
-  const bool fok = f < g.F;
+  const bool fok = active && f < g.F;
   const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
   auto bload = [&](int ib, int s) {
     const int i = 16 * ib + 4 * s + lk;
-    const bool ok = fok && i < np;
-    const int l = ok ? m + p + 2 * i : m;
-    const float v = yf[(fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1)];
-    return ok ? v : 0.f;
+    const int l = i < np ? m + p + 2 * i : m;
+    return yf[(fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1)];
   };
   floatx4 acc[KR];
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  v4f ring[D];
+  if (nb > 0) {
+    // Stage u issues the copies of stage u+2 and, when u opens a row block,
+    // then the B loads of the next row block.  The loads issued after the
+    // copies of stage s, which its wait has to leave in flight, are those
+    // of stage s+1 and the B loads issued at stages s-2 and s-1.  The
+    // prologue plays stages -2 and -1 the same way.
+    float bn[4], bc[4];
+    constexpr bool b_after_first = (PARTS == 2);  // stage -2 opens a row block
+    if (!b_after_first) {
 #pragma unroll
-  for (int u = 0; u < D; ++u) ring[u] = A[static_cast<size_t>(min(u, last)) * 64];
-  float bn[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
-  for (int ib = 0; ib < nbp; ++ib) {
-    float bc[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) bc[s] = bn[s];
-    if (ib + 1 < nbp) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bn[s] = bload(ib + 1, s);
+      for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
+      asm volatile("" ::: "memory");
     }
+    issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
+    if (b_after_first) {
+      asm volatile("" ::: "memory");
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-#pragma unroll
-      for (int t = 0; t < T4; ++t) {
-        const int st = s * T4 + t;
-        const v4f av = ring[st % D];
-        const int q = ib * STEPS + st + D;
-        ring[st % D] = A[static_cast<size_t>(min(q, last)) * 64];
-        acc[4 * t + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bc[s], acc[4 * t + 0], 0, 0, 0);
-        acc[4 * t + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bc[s], acc[4 * t + 1], 0, 0, 0);
-        acc[4 * t + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bc[s], acc[4 * t + 2], 0, 0, 0);
-        acc[4 * t + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bc[s], acc[4 * t + 3], 0, 0, 0);
-      }
+      for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
+      asm volatile("" ::: "memory");
     }
+    issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
+    for (int st0 = 0; st0 < nst; st0 += S::NST) {
+      unrolled<0, S::NST>([&](auto su_c) {
+        constexpr int su = decltype(su_c)::value;
+        constexpr int part = su % PARTS;
+        const int st = st0 + su;
+        if (st >= nst) return false;
+        v4f* cur = ring_buf<su>(b0, b1, b2);
+        v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
+        // B loads issued after this stage's copies: at stage s-2 (if part 0
+        // there) and at stage s-1 (if part 0 there)
+        constexpr int pm2 = (part + 2 * PARTS - 2) % PARTS, pm1 = (part + PARTS - 1) % PARTS;
+        constexpr int nb_after = (pm2 == 0 ? 4 : 0) + (pm1 == 0 ? 4 : 0);
+        __builtin_amdgcn_s_waitcnt(vm_wait(LPW + nb_after));
+        stage_barrier();
+        const int ib = st / PARTS;
+        if constexpr (part == 0) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bc[q] = bn[q];
+        }
+        issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
+        if constexpr (part == 0) {
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bn[q] = bload(ib + 1, q);
+          asm volatile("" ::: "memory");
+        }
+        if (active && ib < nbp) {
+#pragma unroll
+          for (int tt = 0; tt < SC; ++tt) {
+            const int e = part * SC + tt;
+            const int s = e / TS, t = e - s * TS;
+            const v4f av = cur[(p * SC + tt) * 64 + lane];
+            const float bv = bc[s];
+            acc[4 * t + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv, acc[4 * t + 0], 0, 0, 0);
+            acc[4 * t + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv, acc[4 * t + 1], 0, 0, 0);
+            acc[4 * t + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv, acc[4 * t + 2], 0, 0, 0);
+            acc[4 * t + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv, acc[4 * t + 3], 0, 0, 0);
+          }
+        }
+        return true;
+      });
+    }
+    __builtin_amdgcn_s_waitcnt(vm_wait(0));
   }
+  if (!active) return;
   float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16;
   // acc[4t + q][r] is output row 4 lk + r, ring k = (4 lk + r) * KR + 4 t + q
 #pragma unroll
-  for (int t = 0; t < T4; ++t)
+  for (int t = 0; t < TS; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -196,12 +326,12 @@ template <int NCB, int KS>
 hipError_t launch_pair(bool analysis, const LegArgs& a, const void* in, void* out, float c_rest, hipStream_t st) {
   if (analysis) {
     const unsigned blocks = static_cast<unsigned>(8 * a.work_per);
-    hipLaunchKernelGGL((analysis_kernel<NCB, KS>), dim3(blocks), dim3(128 * NCB), 0, st, a, a.work, a.work_per,
+    hipLaunchKernelGGL((analysis_kernel<NCB, KS>), dim3(blocks), dim3(Stages<NCB, KS>::NTH), 0, st, a, a.work, a.work_per,
                        static_cast<const float*>(in), static_cast<float2*>(out), c_rest);
   } else {
-    const unsigned blocks = static_cast<unsigned>(8 * a.work_syn_per);
-    hipLaunchKernelGGL((synthesis_kernel<NCB, KS>), dim3(blocks), dim3(128 * NCB), 0, st, a, a.work_syn,
-                       a.work_syn_per, static_cast<const float2*>(in), static_cast<float*>(out));
+    const unsigned blocks = static_cast<unsigned>(8 * a.work_per);
+    hipLaunchKernelGGL((synthesis_kernel<NCB, KS>), dim3(blocks), dim3(Stages<NCB, KS>::NTH), 0, st, a, a.work,
+                       a.work_per, static_cast<const float2*>(in), static_cast<float*>(out));
   }
   return hipGetLastError();
 }
@@ -223,8 +353,7 @@ hipError_t dispatch(bool analysis, const LegArgs& a, Storage st, const void* in,
   if (st != Storage::F32) return hipErrorNotSupported;
   switch (a.ncb) {
     case 1: return by_ks<1>(analysis, a, in, out, c_rest, stream);
-    case 3: return by_ks<3>(analysis, a, in, out, c_rest, stream);
-    case 4: return by_ks<4>(analysis, a, in, out, c_rest, stream);
+    case 2: return by_ks<2>(analysis, a, in, out, c_rest, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -238,12 +367,7 @@ int legendre_ring_pad(int nk) {
   return -1;
 }
 
-int legendre_ncb(int groups) {
-  if (groups >= 4 && groups % 4 == 0) return 4;
-  if (groups >= 3 && groups % 3 == 0) return 3;
-  if (groups >= 8) return 4;
-  return 1;
-}
+int legendre_ncb(int groups) { return groups >= 2 ? 2 : 1; }
 
 hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y, float c_rest,
                                     hipStream_t stream) {

@@ -132,14 +132,17 @@ __global__ __launch_bounds__(128 * NCB) void analysis_bf16_kernel(LegArgs a, con
       }
     }
   }
-  // the entries l < m of this chunk's fields are zero
-  const int fbeg = 8 * NCB * c;
-  const int fend = min(g.F, fbeg + 8 * NCB);
-  const int nf = fend - fbeg;
-  for (int e = threadIdx.x; e < m * nf; e += NTH) {
-    const int l = e / nf;
-    const int ff = fbeg + (e - l * nf);
-    y[(static_cast<size_t>(ff) * g.lmax + l) * g.mmax + m] = make_float2(0.f, 0.f);
+  // zeros of the spectrum: degree l = m, orders m+1 .. mmax-1 of this
+  // chunk's fields (contiguous runs; together the workgroups of all m cover
+  // every entry l < m')
+  if (m < g.lmax) {
+    const int fbeg = 8 * NCB * c;
+    const int fend = min(g.F, fbeg + 8 * NCB);
+    const int run = g.mmax - 1 - m;
+    for (int ff = fbeg; ff < fend; ++ff) {
+      float2* row = y + (static_cast<size_t>(ff) * g.lmax + m) * g.mmax + m + 1;
+      for (int e = threadIdx.x; e < run; e += NTH) row[e] = make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -222,8 +225,8 @@ hipError_t launch3(bool analysis, const LegArgs& a, const void* in, void* out, f
     hipLaunchKernelGGL((analysis_bf16_kernel<NCB, KS, NP>), dim3(8 * a.work_per), dim3(128 * NCB), 0, st, a,
                        a.work, a.work_per, static_cast<const float*>(in), static_cast<float2*>(out), c_rest);
   } else {
-    hipLaunchKernelGGL((synthesis_bf16_kernel<NCB, KS, NP>), dim3(8 * a.work_syn_per), dim3(128 * NCB), 0, st, a,
-                       a.work_syn, a.work_syn_per, static_cast<const float2*>(in), static_cast<float*>(out));
+    hipLaunchKernelGGL((synthesis_bf16_kernel<NCB, KS, NP>), dim3(8 * a.work_per), dim3(128 * NCB), 0, st, a,
+                       a.work, a.work_per, static_cast<const float2*>(in), static_cast<float*>(out));
   }
   return hipGetLastError();
 }
@@ -256,8 +259,7 @@ hipError_t dispatch(bool analysis, int planes, const LegArgs& a, const void* in,
                     hipStream_t st) {
   switch (a.ncb) {
     case 1: return by_ks<1>(analysis, planes, a, in, out, c_rest, st);
-    case 3: return by_ks<3>(analysis, planes, a, in, out, c_rest, st);
-    case 4: return by_ks<4>(analysis, planes, a, in, out, c_rest, st);
+    case 2: return by_ks<2>(analysis, planes, a, in, out, c_rest, st);
     default: return hipErrorInvalidValue;
   }
 }
