@@ -16,7 +16,10 @@
 //    (re, im) of those fields.  A workgroup writes / reads 32-byte runs; the
 //    block order is remapped so that the workgroups completing one 128-byte
 //    line run together on the same XCD (which merges them in its L2).
+#include <algorithm>
+
 #include "internal.h"
+#include "kernel_common.h"
 
 namespace sht {
 namespace {
@@ -198,12 +201,27 @@ struct Codelet<10> : Composite<2, 5> {};
 template <>
 struct Codelet<16> : Composite<4, 4> {};
 
+// Twiddles e^{-2 pi i e / N} from a two-level table in LDS: T1[i] =
+// w^{32 i} (i < ceil(N/32)) followed by T2[j] = w^j (j < 32), both copied
+// from the float64-rounded global table; w^e = T1[e / 32] T2[e % 32].  The
+// FFT passes read them from LDS instead of issuing a chain of dependent
+// global loads per butterfly.
+__host__ __device__ constexpr int twiddle_lds_entries(int n) { return (n + 31) / 32 + 32; }
+__device__ __forceinline__ void load_twiddles(float2* ltw, int n, const float2* __restrict__ tw) {
+  const int n1 = (n + 31) / 32;
+  for (int i = threadIdx.x; i < n1 + 32; i += blockDim.x) ltw[i] = i < n1 ? tw[32 * i] : tw[(i - n1) % n];
+}
+__device__ __forceinline__ float2 twiddle(const float2* ltw, int n, int e) {
+  const int n1 = (n + 31) / 32;
+  return cmul(ltw[e >> 5], ltw[n1 + (e & 31)]);
+}
+
 // One in-place Stockham pass of radix R over FGW sequences of length N held
 // in LDS; P is the product of the radices of the earlier passes.  Every
 // thread first gathers the inputs of all its butterflies into registers,
 // then (after a barrier) overwrites the buffer with their outputs.
 template <int N, int R, int P>
-__device__ __forceinline__ void pass_inplace(float2* buf, const float2* __restrict__ tw, float sg) {
+__device__ __forceinline__ void pass_inplace(float2* buf, const float2* ltw, float sg) {
   constexpr int NB = N / R;
   constexpr int TOT = FGW * NB;
   constexpr int PER = (TOT + NT - 1) / NT;
@@ -219,7 +237,7 @@ __device__ __forceinline__ void pass_inplace(float2* buf, const float2* __restri
       for (int q = 0; q < R; ++q) v[b][q] = buf[f * N + t + q * NB];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int b = 0; b < PER; ++b) {
     const int bi = threadIdx.x + b * NT;
@@ -230,7 +248,7 @@ __device__ __forceinline__ void pass_inplace(float2* buf, const float2* __restri
       if (P > 1 && k != 0) {
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          float2 w = tw[q * k * TS];
+          float2 w = twiddle(ltw, N, q * k * TS);
           if (sg > 0.f) w.y = -w.y;  // table holds e^{-2 pi i j / N}
           v[b][q] = cmul(v[b][q], w);
         }
@@ -241,18 +259,25 @@ __device__ __forceinline__ void pass_inplace(float2* buf, const float2* __restri
       for (int q = 0; q < R; ++q) buf[ob + q * P] = v[b][q];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-template <int N, int R1, int R2, int R3>
+template <int N_, int R1, int R2, int R3>
 struct FastFFT {
+  static constexpr int N = N_;
   static constexpr int kLdsComplex = FGW * N;  // single in-place buffer
-  __device__ static __forceinline__ float2* run(float2* buf, const DftArgs&, const float2* __restrict__ tw,
+  // twiddle table in LDS right after the FFT buffer
+  static constexpr size_t kLdsBytes = (static_cast<size_t>(kLdsComplex) + twiddle_lds_entries(N)) * sizeof(float2);
+  __device__ static __forceinline__ void prepare(float2* buf, const DftArgs&, const float2* __restrict__ tw) {
+    load_twiddles(buf + kLdsComplex, N, tw);
+  }
+  __device__ static __forceinline__ float2* run(float2* buf, const DftArgs&, const float2* __restrict__,
                                                 float sg) {
     static_assert(R1 * R2 * R3 == N, "radix plan");
-    pass_inplace<N, R1, 1>(buf, tw, sg);
-    pass_inplace<N, R2, R1>(buf, tw, sg);
-    if constexpr (R3 > 1) pass_inplace<N, R3, R1 * R2>(buf, tw, sg);
+    const float2* ltw = buf + kLdsComplex;
+    pass_inplace<N, R1, 1>(buf, ltw, sg);
+    pass_inplace<N, R2, R1>(buf, ltw, sg);
+    if constexpr (R3 > 1) pass_inplace<N, R3, R1 * R2>(buf, ltw, sg);
     return buf;
   }
 };
@@ -280,6 +305,7 @@ __device__ __forceinline__ void pingpong_bfly(const float2* __restrict__ src, fl
 }
 
 struct GenericFFT {
+  __device__ static __forceinline__ void prepare(float2*, const DftArgs&, const float2* __restrict__) {}
   __device__ static float2* run(float2* src, const DftArgs& a, const float2* __restrict__ tw, float sg) {
     const int N = a.nlon;
     float2* dst = src + FGW * N;
@@ -349,6 +375,7 @@ __global__ __launch_bounds__(NT) void dft_forward_kernel(DftArgs a, const float*
   const int ks = a.nlat - 1 - kk;
   const bool eq = (ks == kk);
   const int f0 = 8 * it.g + 4 * it.hh;
+  FFT::prepare(lds, a, tw);
   // load 4 fields x 2 rings, packed as complex (north, mirrored ring)
   const int nq = N / 4;
   if ((N & 3) == 0) {
@@ -430,6 +457,7 @@ __global__ __launch_bounds__(NT) void dft_inverse_kernel(DftArgs a, const float*
   const int ks = a.nlat - 1 - kk;
   const bool eq = (ks == kk);
   const int f0 = 8 * it.g + 4 * it.hh;
+  FFT::prepare(lds, a, tw);
   for (int idx = threadIdx.x; idx < FGW * N; idx += NT) lds[idx] = make_float2(0.f, 0.f);
   __syncthreads();
   const float h = 0.5f * a.c_rest;
@@ -535,11 +563,15 @@ template <bool FORWARD>
 hipError_t dispatch(const DftArgs& a, const float* in, float* out, const float2* tw, const float* scale,
                     hipStream_t st) {
   const size_t one = static_cast<size_t>(FGW) * a.nlon * sizeof(float2);
+  using F1440 = FastFFT<1440, 9, 10, 16>;
+  using F720 = FastFFT<720, 9, 5, 16>;
+  using F360 = FastFFT<360, 9, 5, 8>;
+  using F64 = FastFFT<64, 4, 16, 1>;
   switch (a.nlon) {
-    case 1440: return launch_with<FORWARD, FastFFT<1440, 9, 10, 16>>(a, one, in, out, tw, scale, st);
-    case 720: return launch_with<FORWARD, FastFFT<720, 9, 5, 16>>(a, one, in, out, tw, scale, st);
-    case 360: return launch_with<FORWARD, FastFFT<360, 9, 5, 8>>(a, one, in, out, tw, scale, st);
-    case 64: return launch_with<FORWARD, FastFFT<64, 4, 16, 1>>(a, one, in, out, tw, scale, st);
+    case 1440: return launch_with<FORWARD, F1440>(a, F1440::kLdsBytes, in, out, tw, scale, st);
+    case 720: return launch_with<FORWARD, F720>(a, F720::kLdsBytes, in, out, tw, scale, st);
+    case 360: return launch_with<FORWARD, F360>(a, F360::kLdsBytes, in, out, tw, scale, st);
+    case 64: return launch_with<FORWARD, F64>(a, F64::kLdsBytes, in, out, tw, scale, st);
     default: return launch_with<FORWARD, GenericFFT>(a, 2 * one, in, out, tw, scale, st);
   }
 }

@@ -42,3 +42,18 @@ __device__ __forceinline__ void stage_barrier() {
 }
 
 }  // namespace sht
+
+namespace sht {
+
+// Workgroup barrier for data exchanged through LDS only: the wave waits for
+// its own LDS operations (lgkmcnt(0)), then s_barrier.  Unlike
+// __syncthreads(), whose release fence also waits for every outstanding
+// global load and store (vmcnt(0)), it leaves prefetches in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+}  // namespace sht
