@@ -63,6 +63,12 @@ struct Stages {
   // own beyond the ones written here.
   static constexpr int PERIOD = PARTS == 3 ? 3 : 6;
   static constexpr int NST = ((PARTS * T4 + PERIOD - 1) / PERIOD) * PERIOD;
+  // Analysis: the waves' K slices of S / A come through the same ring
+  // first, in XS stages that carry 16 rings of every lane group of every
+  // wave (4 pieces of 1 KiB per wave), when a buffer holds them.
+  static constexpr bool XSTREAM = (2 * SC >= 4 * NW) && (KS % 16 == 0);
+  static constexpr int XS = XSTREAM ? KS / 16 : 0;
+  static constexpr int LPWX = 4;
 };
 
 // Calls f(integral_constant<U>) for U = 0, 1, ..., END-1 as straight-line
@@ -127,11 +133,12 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const int nst = PARTS * nb;
   const float* tab = static_cast<const float*>(a.tab_ana) + a.tab_off[m];
   float xr[KS];
-  {
-    // idle waves (past the last field group) load group 0 and never use it
-    const float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + (active ? cb : 0)) * KPAD * 16 + lk * KS * 16 + li;
+  // this wave's K slice: S or A of its parity and field group (idle waves,
+  // past the last field group, read group 0 and never use it)
+  const float* Wg = W + (static_cast<size_t>(2 * m + p) * g.groups + (active ? cb : 0)) * KPAD * 16;
+  if constexpr (!S::XSTREAM) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) xr[s] = Wp[16 * s];
+    for (int s = 0; s < KS; ++s) xr[s] = Wg[(lk * KS + s) * 16 + li];
   }
   const float ms = (m == 0) ? 1.f : c_rest;
   float* yf = reinterpret_cast<float*>(y);
@@ -141,8 +148,41 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
     // Every stage issues the copies of stage s+2, past the end too, so that
     // each wave always has exactly LPW copies in flight behind the ones it
     // waits for and every wait is the same vm_wait(LPW).
-    issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
-    issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
+    constexpr int XS = S::XS;
+    if constexpr (S::XSTREAM) {
+      // Stage u < XS: every wave copies rings lk * KS + 16u .. +15 of its
+      // slice (1 KiB, contiguous in W) for each lane group lk into piece
+      // 4 wave + lk of the buffer, then reads its 16 values of xr from there.
+      // Table stage s follows as stage XS + s.
+      auto issue_x = [&](v4f* B, int u) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          __builtin_amdgcn_global_load_lds(Wg + (q * KS + 16 * u) * 16 + lane * 4, B + (4 * wave + q) * 64, 16, 0, 0);
+      };
+      issue_x(b0, 0);
+      if constexpr (XS > 1)
+        issue_x(b1, 1);
+      else
+        issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 0, wave, lane);
+      unrolled<0, XS>([&](auto u_c) {
+        constexpr int u = decltype(u_c)::value;
+        v4f* cur = ring_buf<u>(b0, b1, b2);
+        v4f* nxt = ring_buf<u + 2>(b0, b1, b2);
+        __builtin_amdgcn_s_waitcnt(vm_wait(u + 1 < XS ? S::LPWX : LPW));
+        stage_barrier();
+        if constexpr (u + 2 < XS)
+          issue_x(nxt, u + 2);
+        else
+          issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, u + 2 - XS, wave, lane);
+        const float* xb = reinterpret_cast<const float*>(cur) + (4 * wave + lk) * 256 + li;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xr[16 * u + r] = xb[16 * r];
+        return true;
+      });
+    } else {
+      issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
+      issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
+    }
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int st0 = 0; st0 < nst; st0 += S::NST) {
       unrolled<0, S::NST>([&](auto su_c) {
@@ -150,8 +190,8 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
         constexpr int part = su % PARTS;
         const int st = st0 + su;
         if (st >= nst) return false;
-        v4f* cur = ring_buf<su>(b0, b1, b2);
-        v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
+        v4f* cur = ring_buf<su + XS>(b0, b1, b2);
+        v4f* nxt = ring_buf<su + XS + 2>(b0, b1, b2);
         __builtin_amdgcn_s_waitcnt(vm_wait(LPW));
         stage_barrier();
         issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
