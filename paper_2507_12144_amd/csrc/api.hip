@@ -142,6 +142,10 @@ struct sht_plan_s {
   hipStream_t stream = nullptr;
   int device = 0;
   size_t grid_elems = 0, spec_elems = 0;
+  // batched launches: segment table and plan-wide Legendre work list
+  sht::SegDev* d_segs = nullptr;
+  int2* bwork = nullptr;
+  sht::BatchArgs batch{};
 };
 
 namespace sht {
@@ -293,6 +297,100 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   return SHT_OK;
 }
 
+// Plan-wide work list of the batched float32 Legendre kernels: items
+// {m, (segment << 16) | column chunk of kBatchNcb field groups}.  Orders come
+// in chunks of 16 consecutive m of one segment (their 8-byte spectrum
+// entries share 128-byte lines); chunks go to the 8 XCDs largest first, each
+// to the XCD with the least work so far (greedy LPT), and each XCD takes its
+// chunks largest first.  The work of an item is its number of 16-row blocks
+// plus one.
+std::vector<int2> batched_worklist(const std::vector<Segment>& segs, int chunk_m, size_t* per_out) {
+  struct Chunk {
+    int seg, m0, m1;
+    int64_t work;
+  };
+  std::vector<Chunk> chunks;
+  for (int si = 0; si < static_cast<int>(segs.size()); ++si) {
+    const sht_desc& d = segs[si].d;
+    const int cpm = (segs[si].g.groups + kBatchNcb - 1) / kBatchNcb;
+    for (int m0 = 0; m0 < d.mmax; m0 += chunk_m) {
+      Chunk c{si, m0, std::min(d.mmax, m0 + chunk_m), 0};
+      for (int m = c.m0; m < c.m1; ++m) c.work += static_cast<int64_t>(cpm) * ((((d.lmax - m + 1) >> 1) + 15) / 16 + 1);
+      chunks.push_back(c);
+    }
+  }
+  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& a, const Chunk& b) { return a.work > b.work; });
+  std::vector<std::vector<int2>> slices(8);
+  std::vector<int64_t> load(8, 0);
+  for (const Chunk& c : chunks) {
+    const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += c.work;
+    const int cpm = (segs[c.seg].g.groups + kBatchNcb - 1) / kBatchNcb;
+    for (int m = c.m0; m < c.m1; ++m)
+      for (int k = 0; k < cpm; ++k) slices[x].push_back(make_int2(m, (c.seg << 16) | k));
+  }
+  size_t per = 1;
+  for (auto& v : slices) per = std::max(per, v.size());
+  std::vector<int2> flat;
+  flat.reserve(8 * per);
+  for (auto& v : slices) {
+    v.resize(per, make_int2(-1, -1));
+    flat.insert(flat.end(), v.begin(), v.end());
+  }
+  *per_out = per;
+  return flat;
+}
+
+// Device segment table, DFT item numbering and (float32) the batched
+// Legendre work list of a plan whose segments are built.
+sht_status build_batch(sht_plan_s* p, int chunk_m) {
+  std::vector<SegDev> h(p->segs.size());
+  int items = 0;
+  size_t lds = 0;
+  for (size_t i = 0; i < p->segs.size(); ++i) {
+    const Segment& S = p->segs[i];
+    SegDev& d = h[i];
+    d.g = S.g;
+    d.tab_ana = S.tab_ana;
+    d.tab_syn = S.tab_syn;
+    d.tab_off = S.tab_off;
+    d.work = S.work;
+    d.scale_sht = S.scale_sht;
+    d.scale_one = S.scale_one;
+    d.tw = S.tw;
+    d.grid_off = static_cast<long long>(S.grid_off);
+    d.spec_off = static_cast<long long>(S.spec_off);
+    d.dft_begin = items;
+    d.dft_items = 2 * S.g.groups * S.g.nk;
+    d.nstages = S.dp.nstages;
+    for (int r = 0; r < kMaxRadices; ++r) d.radix[r] = S.dp.radix[r];
+    items += d.dft_items;
+    lds = std::max(lds, dft_lds_bytes(S.g.nlon));
+  }
+  if (p->d_segs) {
+    (void)hipFree(p->d_segs);
+    p->d_segs = nullptr;
+  }
+  sht_status rc = upload(&p->d_segs, h, p->stream, "segment table");
+  if (rc != SHT_OK) return rc;
+  p->batch.segs = p->d_segs;
+  p->batch.nseg = static_cast<int>(h.size());
+  p->batch.dft_total = items;
+  p->batch.dft_lds = lds;
+  if (p->storage == Storage::F32) {
+    size_t per = 0;
+    std::vector<int2> flat = batched_worklist(p->segs, chunk_m, &per);
+    if (p->bwork) {
+      (void)hipFree(p->bwork);
+      p->bwork = nullptr;
+    }
+    if ((rc = upload(&p->bwork, flat, p->stream, "batched work list")) != SHT_OK) return rc;
+    p->batch.work = p->bwork;
+    p->batch.work_per = static_cast<int>(per);
+  }
+  return SHT_OK;
+}
+
 LegArgs leg_args(const Segment& S) {
   LegArgs a{};
   a.g = S.g;
@@ -354,49 +452,46 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
     e = hipSetDevice(plan->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   }
-  sht_status rc = SHT_OK;
-  for (Segment& S : plan->segs) {
-    const SegGeom& g = S.g;
-    switch (op) {
-      case Op::SHT:
-      case Op::ISHT_T: {
-        const float* x = static_cast<const float*>(in) + S.grid_off;
-        float2* y = static_cast<float2*>(out) + S.spec_off;
-        const bool fwd = (op == Op::SHT);
-        e = timed(plan, K_DFT_FWD, st, [&] {
-          return launch_dft_forward(g, S.dp, x, S.work, S.tw, fwd ? S.scale_sht : S.scale_one, st);
-        });
-        if (e == hipSuccess)
-          e = timed(plan, K_LEG_ANA, st, [&] {
-            const int planes = storage_planes(plan->storage);
-            return planes ? launch_legendre_analysis_bf16(leg_args(S), planes, S.work, y, fwd ? 1.f : 2.f, st)
-                          : launch_legendre_analysis(leg_args(S), plan->storage, S.work, y, fwd ? 1.f : 2.f, st);
-          });
-        break;
-      }
-      case Op::ISHT:
-      case Op::SHT_T: {
-        const float2* y = static_cast<const float2*>(in) + S.spec_off;
-        float* x = static_cast<float*>(out) + S.grid_off;
-        const bool inv = (op == Op::ISHT);
-        e = timed(plan, K_LEG_SYN, st, [&] {
-          const int planes = storage_planes(plan->storage);
-          return planes ? launch_legendre_synthesis_bf16(leg_args(S), planes, y, S.work, st)
-                        : launch_legendre_synthesis(leg_args(S), plan->storage, y, S.work, st);
-        });
-        if (e == hipSuccess)
-          e = timed(plan, K_DFT_INV, st, [&] {
-            return launch_dft_inverse(g, S.dp, S.work, x, S.tw, inv ? S.scale_one : S.scale_sht, inv ? 2.f : 1.f,
-                                      st);
-          });
-        break;
-      }
+  // One launch per stage covers every segment (float32); the bf16 forms
+  // run their Legendre step per segment.
+  const int planes = storage_planes(plan->storage);
+  const BatchArgs& B = plan->batch;
+  auto legendre = [&](bool analysis, const void* src, void* dst, float c_rest) -> hipError_t {
+    if (!planes)
+      return analysis ? launch_legendre_analysis_batched(B, static_cast<float2*>(dst), c_rest, st)
+                      : launch_legendre_synthesis_batched(B, static_cast<const float2*>(src), st);
+    for (Segment& S : plan->segs) {
+      hipError_t e2 =
+          analysis ? launch_legendre_analysis_bf16(leg_args(S), planes, S.work,
+                                                   static_cast<float2*>(dst) + S.spec_off, c_rest, st)
+                   : launch_legendre_synthesis_bf16(leg_args(S), planes, static_cast<const float2*>(src) + S.spec_off,
+                                                    S.work, st);
+      if (e2 != hipSuccess) return e2;
     }
-    if (e != hipSuccess) {
-      rc = hip_fail(e, "kernel launch");
+    return hipSuccess;
+  };
+  switch (op) {
+    case Op::SHT:
+    case Op::ISHT_T: {
+      const bool fwd = (op == Op::SHT);
+      e = timed(plan, K_DFT_FWD, st,
+                [&] { return launch_dft_forward_batched(B, static_cast<const float*>(in), fwd, st); });
+      if (e == hipSuccess) e = timed(plan, K_LEG_ANA, st, [&] { return legendre(true, nullptr, out, fwd ? 1.f : 2.f); });
+      break;
+    }
+    case Op::ISHT:
+    case Op::SHT_T: {
+      const bool inv = (op == Op::ISHT);
+      e = timed(plan, K_LEG_SYN, st, [&] { return legendre(false, in, nullptr, 1.f); });
+      if (e == hipSuccess)
+        e = timed(plan, K_DFT_INV, st, [&] {
+          return launch_dft_inverse_batched(B, static_cast<float*>(out), !inv, inv ? 2.f : 1.f, st);
+        });
       break;
     }
   }
+  sht_status rc = SHT_OK;
+  if (e != hipSuccess) rc = hip_fail(e, "kernel launch");
   if (cur != plan->device && cur >= 0) (void)hipSetDevice(cur);
   return rc;
 }
@@ -449,6 +544,14 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
   }
   p->grid_elems = goff;
   p->spec_elems = soff;
+  sht_status rc = build_batch(p, 16);
+  if (rc != SHT_OK) {
+    for (Segment& T : p->segs) free_segment(T);
+    if (p->d_segs) (void)hipFree(p->d_segs);
+    if (p->bwork) (void)hipFree(p->bwork);
+    delete p;
+    return rc;
+  }
   *out = p;
   return SHT_OK;
 }
@@ -459,6 +562,8 @@ sht_status sht_plan_destroy(sht_plan_t plan) {
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
   for (Segment& S : plan->segs) free_segment(S);
+  if (plan->d_segs) (void)hipFree(plan->d_segs);
+  if (plan->bwork) (void)hipFree(plan->bwork);
   for (const TimedLaunch& t : plan->pending) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);

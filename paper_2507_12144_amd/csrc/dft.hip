@@ -31,7 +31,7 @@ struct DftArgs {
   int nlat, nlon, lmax, mmax, nk, F, kpad, G;
   int nitems;              // G * nk * 2 workgroup items
   int nstages;
-  int radix[kMaxRadices];
+  const int* radix;        // the segment's radix plan (device memory)
   float c_rest;
 };
 
@@ -338,24 +338,21 @@ struct GenericFFT {
   }
 };
 
-// Workgroup -> (field group g, ring kk, half hh).  Items are ordered
-// (g, kk, hh) and each XCD (the hardware deals workgroups to the 8 XCDs
-// round-robin) receives one contiguous slice of that order.
+// Item (field group g, ring pair kk, half hh) of a segment, numbered in the
+// order (g, kk, hh); the four items that complete a 128-byte line of W are
+// consecutive.
 struct Item {
   int g, kk, hh;
   bool valid;
 };
-__device__ __forceinline__ Item decode_item(const DftArgs& a) {
-  const int per = (a.nitems + 7) / 8;
-  const int slot = (blockIdx.x % 8) * per + blockIdx.x / 8;
+__device__ __forceinline__ Item item_of(const DftArgs& a, int local) {
   Item it;
-  it.valid = slot < a.nitems;
   const int two_nk = 2 * a.nk;
-  it.g = slot / two_nk;
-  const int rem = slot - it.g * two_nk;
+  it.g = local / two_nk;
+  const int rem = local - it.g * two_nk;
   it.kk = rem >> 1;
   it.hh = rem & 1;
-  if (it.valid && 8 * it.g + 4 * it.hh >= a.F) it.valid = false;
+  it.valid = 8 * it.g + 4 * it.hh < a.F;
   return it;
 }
 
@@ -364,12 +361,9 @@ __device__ __forceinline__ size_t wrow(const DftArgs& a, int m, int p, int g, in
 }
 
 template <class FFT>
-__global__ __launch_bounds__(NT) void dft_forward_kernel(DftArgs a, const float* __restrict__ x,
-                                                         float* __restrict__ W, const float2* __restrict__ tw,
-                                                         const float* __restrict__ ring_scale) {
-  extern __shared__ float2 lds[];
-  const Item it = decode_item(a);
-  if (!it.valid) return;
+__device__ __forceinline__ void dft_forward_body(const DftArgs& a, const Item& it, const float* __restrict__ x,
+                                                 float* __restrict__ W, const float2* __restrict__ tw,
+                                                 const float* __restrict__ ring_scale, float2* lds) {
   const int N = a.nlon;
   const int kk = it.kk;
   const int ks = a.nlat - 1 - kk;
@@ -446,12 +440,9 @@ __global__ __launch_bounds__(NT) void dft_forward_kernel(DftArgs a, const float*
 }
 
 template <class FFT>
-__global__ __launch_bounds__(NT) void dft_inverse_kernel(DftArgs a, const float* __restrict__ W,
-                                                         float* __restrict__ x, const float2* __restrict__ tw,
-                                                         const float* __restrict__ ring_scale) {
-  extern __shared__ float2 lds[];
-  const Item it = decode_item(a);
-  if (!it.valid) return;
+__device__ __forceinline__ void dft_inverse_body(const DftArgs& a, const Item& it, const float* __restrict__ W,
+                                                 float* __restrict__ x, const float2* __restrict__ tw,
+                                                 const float* __restrict__ ring_scale, float2* lds) {
   const int N = a.nlon;
   const int kk = it.kk;
   const int ks = a.nlat - 1 - kk;
@@ -519,61 +510,84 @@ __global__ __launch_bounds__(NT) void dft_inverse_kernel(DftArgs a, const float*
   }
 }
 
-DftArgs make_args(const SegGeom& g, const DftPlan& dp) {
-  DftArgs a{};
-  a.nlat = g.nlat;
-  a.nlon = g.nlon;
-  a.lmax = g.lmax;
-  a.mmax = g.mmax;
-  a.nk = g.nk;
-  a.F = g.F;
-  a.kpad = g.kpad;
-  a.G = g.groups;
-  a.nitems = g.groups * g.nk * 2;
-  a.nstages = dp.nstages;
-  for (int i = 0; i < kMaxRadices; ++i) a.radix[i] = dp.radix[i];
+__device__ __forceinline__ DftArgs seg_args(const SegDev& sd, float c_rest) {
+  DftArgs a;
+  a.nlat = sd.g.nlat;
+  a.nlon = sd.g.nlon;
+  a.lmax = sd.g.lmax;
+  a.mmax = sd.g.mmax;
+  a.nk = sd.g.nk;
+  a.F = sd.g.F;
+  a.kpad = sd.g.kpad;
+  a.G = sd.g.groups;
+  a.nitems = sd.dft_items;
+  a.nstages = sd.nstages;
+  a.radix = sd.radix;
+  a.c_rest = c_rest;
   return a;
 }
 
-template <bool FORWARD, class FFT>
-hipError_t launch_with(const DftArgs& a, size_t lds_bytes, const float* in, float* out, const float2* tw,
-                       const float* scale, hipStream_t st) {
-  const unsigned blocks = static_cast<unsigned>((a.nitems + 7) / 8 * 8);
-  if (FORWARD) {
-    auto k = dft_forward_kernel<FFT>;
-    if (lds_bytes > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds_bytes, st, a, in, out, tw, scale);
-  } else {
-    auto k = dft_inverse_kernel<FFT>;
-    if (lds_bytes > 65536) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(NT), lds_bytes, st, a, in, out, tw, scale);
-  }
-  return hipGetLastError();
+using F1440 = FastFFT<1440, 9, 10, 16>;
+using F720 = FastFFT<720, 9, 5, 16>;
+using F360 = FastFFT<360, 9, 5, 8>;
+using F64 = FastFFT<64, 4, 16, 1>;
+
+// Batched kernels: the items of all segments are numbered consecutively
+// (segment s owns [dft_begin, dft_begin + dft_items)); each XCD (workgroup b
+// runs on XCD b % 8) receives one contiguous slice of that numbering.
+__device__ __forceinline__ int batched_slot(int total) {
+  const int per = (total + 7) / 8;
+  return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+__device__ __forceinline__ int segment_of(const SegDev* __restrict__ segs, int nseg, int slot) {
+  int s = 0;
+  while (s + 1 < nseg && slot >= segs[s + 1].dft_begin) ++s;
+  return s;
 }
 
-template <bool FORWARD>
-hipError_t dispatch(const DftArgs& a, const float* in, float* out, const float2* tw, const float* scale,
-                    hipStream_t st) {
-  const size_t one = static_cast<size_t>(FGW) * a.nlon * sizeof(float2);
-  using F1440 = FastFFT<1440, 9, 10, 16>;
-  using F720 = FastFFT<720, 9, 5, 16>;
-  using F360 = FastFFT<360, 9, 5, 8>;
-  using F64 = FastFFT<64, 4, 16, 1>;
-  switch (a.nlon) {
-    case 1440: return launch_with<FORWARD, F1440>(a, F1440::kLdsBytes, in, out, tw, scale, st);
-    case 720: return launch_with<FORWARD, F720>(a, F720::kLdsBytes, in, out, tw, scale, st);
-    case 360: return launch_with<FORWARD, F360>(a, F360::kLdsBytes, in, out, tw, scale, st);
-    case 64: return launch_with<FORWARD, F64>(a, F64::kLdsBytes, in, out, tw, scale, st);
-    default: return launch_with<FORWARD, GenericFFT>(a, 2 * one, in, out, tw, scale, st);
+__global__ __launch_bounds__(NT) void dft_forward_batched(const SegDev* __restrict__ segs, int nseg, int total,
+                                                          const float* __restrict__ x, int sht_scale) {
+  extern __shared__ float2 lds[];
+  const int slot = batched_slot(total);
+  if (slot >= total) return;
+  const SegDev& sd = segs[segment_of(segs, nseg, slot)];
+  const DftArgs a = seg_args(sd, 1.f);
+  const Item it = item_of(a, slot - sd.dft_begin);
+  if (!it.valid) return;
+  const float* xs = x + sd.grid_off;
+  const float* scale = sht_scale ? sd.scale_sht : sd.scale_one;
+  switch (sd.g.nlon) {
+    case 1440: dft_forward_body<F1440>(a, it, xs, sd.work, sd.tw, scale, lds); break;
+    case 720: dft_forward_body<F720>(a, it, xs, sd.work, sd.tw, scale, lds); break;
+    case 360: dft_forward_body<F360>(a, it, xs, sd.work, sd.tw, scale, lds); break;
+    case 64: dft_forward_body<F64>(a, it, xs, sd.work, sd.tw, scale, lds); break;
+    default: dft_forward_body<GenericFFT>(a, it, xs, sd.work, sd.tw, scale, lds); break;
   }
+}
+
+__global__ __launch_bounds__(NT) void dft_inverse_batched(const SegDev* __restrict__ segs, int nseg, int total,
+                                                          float* __restrict__ x, int sht_scale, float c_rest) {
+  extern __shared__ float2 lds[];
+  const int slot = batched_slot(total);
+  if (slot >= total) return;
+  const SegDev& sd = segs[segment_of(segs, nseg, slot)];
+  const DftArgs a = seg_args(sd, c_rest);
+  const Item it = item_of(a, slot - sd.dft_begin);
+  if (!it.valid) return;
+  float* xs = x + sd.grid_off;
+  const float* scale = sht_scale ? sd.scale_sht : sd.scale_one;
+  switch (sd.g.nlon) {
+    case 1440: dft_inverse_body<F1440>(a, it, sd.work, xs, sd.tw, scale, lds); break;
+    case 720: dft_inverse_body<F720>(a, it, sd.work, xs, sd.tw, scale, lds); break;
+    case 360: dft_inverse_body<F360>(a, it, sd.work, xs, sd.tw, scale, lds); break;
+    case 64: dft_inverse_body<F64>(a, it, sd.work, xs, sd.tw, scale, lds); break;
+    default: dft_inverse_body<GenericFFT>(a, it, sd.work, xs, sd.tw, scale, lds); break;
+  }
+}
+
+hipError_t prepare_lds(const void* k, size_t lds_bytes) {
+  if (lds_bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
 }
 
 }  // namespace
@@ -594,18 +608,32 @@ bool make_dft_plan(int n, DftPlan* p) {
   return r == 1;
 }
 
-hipError_t launch_dft_forward(const SegGeom& g, const DftPlan& dp, const float* x, float* W,
-                              const float2* tw, const float* ring_scale, hipStream_t st) {
-  DftArgs a = make_args(g, dp);
-  return dispatch<true>(a, x, W, tw, ring_scale, st);
+size_t dft_lds_bytes(int nlon) {
+  switch (nlon) {
+    case 1440: return F1440::kLdsBytes;
+    case 720: return F720::kLdsBytes;
+    case 360: return F360::kLdsBytes;
+    case 64: return F64::kLdsBytes;
+    default: return 2 * static_cast<size_t>(FGW) * nlon * sizeof(float2);
+  }
 }
 
-hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* W, float* x,
-                              const float2* tw, const float* ring_scale, float c_rest,
-                              hipStream_t st) {
-  DftArgs a = make_args(g, dp);
-  a.c_rest = c_rest;
-  return dispatch<false>(a, W, x, tw, ring_scale, st);
+hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool sht_scale, hipStream_t st) {
+  hipError_t e = prepare_lds(reinterpret_cast<const void*>(dft_forward_batched), b.dft_lds);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
+  hipLaunchKernelGGL(dft_forward_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x,
+                     sht_scale ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dft_inverse_batched(const BatchArgs& b, float* x, bool sht_scale, float c_rest, hipStream_t st) {
+  hipError_t e = prepare_lds(reinterpret_cast<const void*>(dft_inverse_batched), b.dft_lds);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
+  hipLaunchKernelGGL(dft_inverse_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x,
+                     sht_scale ? 1 : 0, c_rest);
+  return hipGetLastError();
 }
 
 }  // namespace sht

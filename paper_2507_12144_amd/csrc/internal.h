@@ -48,17 +48,55 @@ struct DftPlan {
 };
 bool make_dft_plan(int n, DftPlan* p);
 
-// Forward ring DFT of the ring pairs (k, nlat-1-k), k < nk, multiplied by
-// ring_scale[k], folded into symmetric/antisymmetric parts and written to
-// the workspace W[m][p][g][k][16] (field f = 8g + i at floats 2i, 2i+1).
-hipError_t launch_dft_forward(const SegGeom& g, const DftPlan& dp, const float* x, float* W,
-                              const float2* tw, const float* ring_scale, hipStream_t st);
+
+// ---- batched launches ----------------------------------------------------
+// Per-segment arguments of the batched kernels (an array in device memory;
+// one launch per transform stage covers every segment of a plan).
+struct SegDev {
+  SegGeom g;
+  const void* tab_ana;     // Legendre table, analysis fragment order
+  const void* tab_syn;     // Legendre table, synthesis fragment order
+  const int64_t* tab_off;  // [mmax] first element of order m
+  float* work;             // workspace W[m][p][g][k][16] of the segment
+  const float* scale_sht;  // (2 pi / nlon) w_k
+  const float* scale_one;  // 1
+  const float2* tw;        // e^{-2 pi i j / nlon}
+  long long grid_off;      // first float of the segment in grid buffers
+  long long spec_off;      // first complex of the segment in spectral buffers
+  int dft_begin;           // first DFT item of the segment (plan-wide numbering)
+  int dft_items;           // 2 * groups * nk
+  int nstages;             // DFT radix plan (generic widths)
+  int radix[kMaxRadices];
+};
+// Plan-wide work of the batched kernels.  Legendre items {m, (segment << 16)
+// | column chunk}, 8 XCD slices of per entries padded with {-1, -1}.
+struct BatchArgs {
+  const SegDev* segs;
+  int nseg;
+  const int2* work;
+  int work_per;
+  int dft_total;           // DFT items of all segments
+  size_t dft_lds;          // dynamic LDS of the batched DFT kernels
+};
+// Field groups per column chunk of the batched float32 Legendre kernels.
+constexpr int kBatchNcb = 2;
+// Dynamic LDS the DFT kernels need for ring width nlon.
+size_t dft_lds_bytes(int nlon);
+// Forward ring DFT of every segment's ring pairs (k, nlat-1-k), k < nk,
+// multiplied by the ring scale (sht_scale: (2 pi / nlon) w_k, else 1),
+// folded into symmetric/antisymmetric parts and written to the segment's
+// workspace W[m][p][g][k][16] (field f = 8g + i at floats 2i, 2i+1).
 // Inverse: reads E = W[m][0], O = W[m][1], north = E + O, south = E - O,
 // synthesises sum_m c_m Re(Y e^{i m p}) with c_0 = 1, c_m = c_rest, scales
-// ring k by ring_scale[k] and writes the grid tensor.
-hipError_t launch_dft_inverse(const SegGeom& g, const DftPlan& dp, const float* W, float* x,
-                              const float2* tw, const float* ring_scale, float c_rest,
-                              hipStream_t st);
+// ring k and writes the grid tensor.  x is the plan-wide grid buffer.
+hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool sht_scale, hipStream_t st);
+hipError_t launch_dft_inverse_batched(const BatchArgs& b, float* x, bool sht_scale, float c_rest, hipStream_t st);
+// Batched float32 Legendre steps (y is the plan-wide spectral buffer):
+// analysis y[f][l][m] = mscale_m sum_k P^_l^m(x_k) W[m][p][g][k][..]
+// (p = (l - m) & 1, mscale_0 = 1, mscale_m = c_rest; 0 for l < m);
+// synthesis W[m][p][g][k][..] = sum_{l = m + p + 2i < lmax} P^_l^m(x_k) y[f][l][m].
+hipError_t launch_legendre_analysis_batched(const BatchArgs& b, float2* y, float c_rest, hipStream_t st);
+hipError_t launch_legendre_synthesis_batched(const BatchArgs& b, const float2* y, hipStream_t st);
 
 // ---- legendre.hip --------------------------------------------------------
 // Work lists: 8 slices (one per XCD) of work_per entries, padded with
@@ -77,14 +115,8 @@ struct LegArgs {
 int legendre_ring_pad(int nk);
 // Field groups per column chunk for a segment with `groups` groups.
 int legendre_ncb(int groups);
-// y[f][l][m] = mscale_m sum_k P^_l^m(x_k) W[m][p][g][k][..] (p = (l - m) & 1),
-// mscale_0 = 1, mscale_m = c_rest; y[f][l][m] = 0 for l < m.
-hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y,
-                                    float c_rest, hipStream_t stream);
-// W[m][p][g][k][..] = sum_{l = m + p + 2i < lmax} P^_l^m(x_k) y[f][l][m]
-hipError_t launch_legendre_synthesis(const LegArgs& a, Storage st, const float2* y, float* W,
-                                     hipStream_t stream);
-// bf16 forms (legendre_bf16.hip), same contract with `planes` table planes.
+// bf16 forms (legendre_bf16.hip), per segment, the contract of the batched
+// float32 steps with `planes` table planes.
 hipError_t launch_legendre_analysis_bf16(const LegArgs& a, int planes, const float* W, float2* y, float c_rest,
                                          hipStream_t stream);
 hipError_t launch_legendre_synthesis_bf16(const LegArgs& a, int planes, const float2* y, float* W,

@@ -110,17 +110,12 @@ __device__ __forceinline__ void issue_stage(v4f* B, const float* __restrict__ ta
 // Analysis.  Contraction index k of a wave's K slice = lk * KS + 4t + q for
 // lane group lk, piece t of the row block and component q.
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void analysis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                             const float* __restrict__ W, float2* __restrict__ y,
-                                                             float c_rest) {
+__device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, const float* __restrict__ W,
+                                              float2* __restrict__ y, float c_rest, v4f* b0, v4f* b1, v4f* b2) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, NTH = S::NTH, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
-  __shared__ v4f b0[2 * SC * 64], b1[2 * SC * 64], b2[2 * SC * 64];
-  const int2 wk = take_work(work, per);
-  const int m = wk.x, c = wk.y;
-  if (m < 0) return;
-  const SegGeom& g = a.g;
+  const SegGeom& g = sd.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave / NCB, j = wave - p * NCB;
   const int cb = c * NCB + j;
@@ -131,7 +126,7 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const int np = p ? (g.lmax - m) >> 1 : n0;
   const int nbp = (np + 15) >> 4;
   const int nst = PARTS * nb;
-  const float* tab = static_cast<const float*>(a.tab_ana) + a.tab_off[m];
+  const float* tab = static_cast<const float*>(sd.tab_ana) + sd.tab_off[m];
   float xr[KS];
   // this wave's K slice: S or A of its parity and field group (idle waves,
   // past the last field group, read group 0 and never use it)
@@ -244,19 +239,15 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
 // li, piece t of a substep and component q; contraction row i = 16 ib + 4 s
 // + lk.  Piece e of a row block is substep e / (KR/4), piece e % (KR/4).
 template <int NCB, int KS>
-__global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void synthesis_kernel(LegArgs a, const int2* __restrict__ work, int per,
-                                                              const float2* __restrict__ y, float* __restrict__ W) {
+__device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
+                                               float* __restrict__ W, v4f* b0, v4f* b1, v4f* b2) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
   constexpr int KR = KPAD / 16;  // 16-ring output blocks
   constexpr int TS = KR / 4;     // pieces per substep
   static_assert(KR % 4 == 0 && 4 * TS == T4, "stage geometry");
-  __shared__ v4f b0[2 * SC * 64], b1[2 * SC * 64], b2[2 * SC * 64];
-  const int2 wk = take_work(work, per);
-  const int m = wk.x, c = wk.y;
-  if (m < 0) return;
-  const SegGeom& g = a.g;
+  const SegGeom& g = sd.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave / NCB, j = wave - p * NCB;
   const int cb = c * NCB + j;
@@ -267,7 +258,7 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const int np = p ? (g.lmax - m) >> 1 : n0;
   const int nbp = (np + 15) >> 4;
   const int nst = PARTS * nb;
-  const float* tab = static_cast<const float*>(a.tab_syn) + a.tab_off[m];
+  const float* tab = static_cast<const float*>(sd.tab_syn) + sd.tab_off[m];
   // B operand of lane (li, lk) at substep s of row block ib: re (li even) or
   // im (li odd) of field 8 cb + li/2 at degree l = m + p + 2 (16 ib + 4 s + lk).
   // Rows past the parity's last degree read degree m instead: their table
@@ -362,39 +353,47 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
       for (int r = 0; r < 4; ++r) Wp[((4 * lk + r) * KR + 4 * t + q) * 16 + li] = acc[4 * t + q][r];
 }
 
-template <int NCB, int KS>
-hipError_t launch_pair(bool analysis, const LegArgs& a, const void* in, void* out, float c_rest, hipStream_t st) {
-  if (analysis) {
-    const unsigned blocks = static_cast<unsigned>(8 * a.work_per);
-    hipLaunchKernelGGL((analysis_kernel<NCB, KS>), dim3(blocks), dim3(Stages<NCB, KS>::NTH), 0, st, a, a.work, a.work_per,
-                       static_cast<const float*>(in), static_cast<float2*>(out), c_rest);
-  } else {
-    const unsigned blocks = static_cast<unsigned>(8 * a.work_per);
-    hipLaunchKernelGGL((synthesis_kernel<NCB, KS>), dim3(blocks), dim3(Stages<NCB, KS>::NTH), 0, st, a, a.work,
-                       a.work_per, static_cast<const float2*>(in), static_cast<float*>(out));
+// Largest stage buffer of the instantiated geometries (pieces of 64 v4f).
+constexpr int kMaxStagePieces = 2 * Stages<kBatchNcb, 96>::SC;
+static_assert(2 * Stages<kBatchNcb, 64>::SC <= kMaxStagePieces && 2 * Stages<kBatchNcb, 48>::SC <= kMaxStagePieces,
+              "stage buffer size");
+
+// Batched kernels: a workgroup takes its item {m, (segment << 16) | chunk}
+// from the plan-wide work list and runs the body specialised for the
+// segment's ring padding.  The three LDS buffers are declared here (three
+// distinct variables, so that the compiler can tell the copies into one
+// from the reads of another) and sized for the largest geometry.
+__global__ __launch_bounds__(128 * kBatchNcb) __attribute__((amdgpu_waves_per_eu(3))) void analysis_batched(
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest) {
+  __shared__ v4f b0[kMaxStagePieces * 64], b1[kMaxStagePieces * 64], b2[kMaxStagePieces * 64];
+  const int2 wk = take_work(work, per);
+  if (wk.x < 0) return;
+  const SegDev& sd = segs[wk.y >> 16];
+  const int m = wk.x, c = wk.y & 0xffff;
+  float2* ys = y + sd.spec_off;
+  switch (sd.g.kpad) {
+    case 64: analysis_body<kBatchNcb, 16>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
+    case 128: analysis_body<kBatchNcb, 32>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
+    case 192: analysis_body<kBatchNcb, 48>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
+    case 256: analysis_body<kBatchNcb, 64>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
+    default: analysis_body<kBatchNcb, 96>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
   }
-  return hipGetLastError();
 }
 
-template <int NCB>
-hipError_t by_ks(bool analysis, const LegArgs& a, const void* in, void* out, float c_rest, hipStream_t st) {
-  switch (a.g.kpad / 4) {
-    case 16: return launch_pair<NCB, 16>(analysis, a, in, out, c_rest, st);
-    case 32: return launch_pair<NCB, 32>(analysis, a, in, out, c_rest, st);
-    case 48: return launch_pair<NCB, 48>(analysis, a, in, out, c_rest, st);
-    case 64: return launch_pair<NCB, 64>(analysis, a, in, out, c_rest, st);
-    case 96: return launch_pair<NCB, 96>(analysis, a, in, out, c_rest, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t dispatch(bool analysis, const LegArgs& a, Storage st, const void* in, void* out, float c_rest,
-                    hipStream_t stream) {
-  if (st != Storage::F32) return hipErrorNotSupported;
-  switch (a.ncb) {
-    case 1: return by_ks<1>(analysis, a, in, out, c_rest, stream);
-    case 2: return by_ks<2>(analysis, a, in, out, c_rest, stream);
-    default: return hipErrorInvalidValue;
+__global__ __launch_bounds__(128 * kBatchNcb) __attribute__((amdgpu_waves_per_eu(3))) void synthesis_batched(
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y) {
+  __shared__ v4f b0[kMaxStagePieces * 64], b1[kMaxStagePieces * 64], b2[kMaxStagePieces * 64];
+  const int2 wk = take_work(work, per);
+  if (wk.x < 0) return;
+  const SegDev& sd = segs[wk.y >> 16];
+  const int m = wk.x, c = wk.y & 0xffff;
+  const float2* ys = y + sd.spec_off;
+  switch (sd.g.kpad) {
+    case 64: synthesis_body<kBatchNcb, 16>(sd, m, c, ys, sd.work, b0, b1, b2); break;
+    case 128: synthesis_body<kBatchNcb, 32>(sd, m, c, ys, sd.work, b0, b1, b2); break;
+    case 192: synthesis_body<kBatchNcb, 48>(sd, m, c, ys, sd.work, b0, b1, b2); break;
+    case 256: synthesis_body<kBatchNcb, 64>(sd, m, c, ys, sd.work, b0, b1, b2); break;
+    default: synthesis_body<kBatchNcb, 96>(sd, m, c, ys, sd.work, b0, b1, b2); break;
   }
 }
 
@@ -409,14 +408,16 @@ int legendre_ring_pad(int nk) {
 
 int legendre_ncb(int groups) { return groups >= 2 ? 2 : 1; }
 
-hipError_t launch_legendre_analysis(const LegArgs& a, Storage st, const float* W, float2* y, float c_rest,
-                                    hipStream_t stream) {
-  return dispatch(true, a, st, W, y, c_rest, stream);
+hipError_t launch_legendre_analysis_batched(const BatchArgs& b, float2* y, float c_rest, hipStream_t st) {
+  hipLaunchKernelGGL(analysis_batched, dim3(static_cast<unsigned>(8 * b.work_per)), dim3(128 * kBatchNcb), 0, st,
+                     b.segs, b.work, b.work_per, y, c_rest);
+  return hipGetLastError();
 }
 
-hipError_t launch_legendre_synthesis(const LegArgs& a, Storage st, const float2* y, float* W,
-                                     hipStream_t stream) {
-  return dispatch(false, a, st, y, W, 1.f, stream);
+hipError_t launch_legendre_synthesis_batched(const BatchArgs& b, const float2* y, hipStream_t st) {
+  hipLaunchKernelGGL(synthesis_batched, dim3(static_cast<unsigned>(8 * b.work_per)), dim3(128 * kBatchNcb), 0, st,
+                     b.segs, b.work, b.work_per, y);
+  return hipGetLastError();
 }
 
 }  // namespace sht

@@ -338,3 +338,64 @@ def test_full_size_equiangular_721_bf16_forms(pkg, prec):
          f"worst degree max-err {mx.max():.3e} (l={int(mx.argmax())})")
     assert max(e1, e2) <= PREC_TOL[prec]
     plan.close()
+
+
+BATCH_MIX = [
+    # segments of one plan: every ring padding (kpad 64 .. 384) and DFT path
+    (33, 64, 17, 17, 0, 1, 3),
+    (45, 90, 40, 40, 2, 1, 2),       # generic-radix ring DFT
+    (181, 360, 180, 180, 0, 1, 5),   # kpad 128
+    (32, 64, 32, 32, 1, 2, 2),
+    (361, 720, 360, 360, 0, 1, 2),   # kpad 192
+    (401, 720, 300, 300, 1, 1, 1),   # kpad 256 (Gauss, 201 northern rings)
+    (721, 1440, 720, 720, 0, 1, 1),  # kpad 384
+]
+
+
+def _batched_io(P, plan, shapes, seed):
+    """Flat inputs of a multi-segment plan, filled segment by segment."""
+    rng = np.random.default_rng(seed)
+    u = np.zeros(plan.grid_elems, np.float32)
+    a = np.zeros(plan.spec_elems, np.complex64)
+    parts = []
+    for i, (nlat, nlon, lmax, mmax, grid, B, C) in enumerate(shapes):
+        go, so = plan.segment(i)
+        ui = rng.standard_normal((B, C, nlat, nlon)).astype(np.float32)
+        ai = synth.coefficients(seed + 7 + i, B, C, lmax, mmax).astype(np.complex64)
+        u[go:go + ui.size] = ui.ravel()
+        a[so:so + ai.size] = ai.ravel()
+        parts.append((go, so, ui, ai))
+    return u, a, parts
+
+
+def test_batched_uneven_segments(pkg):
+    """One plan over segments of every ring padding and both ring-DFT paths:
+    each segment's four transforms against the oracle, and bitwise equal to
+    a single-segment plan of the same shape (the same kernel body runs)."""
+    _say("batched plan over", len(BATCH_MIX), "segments")
+    plan = pkg.Plan([dict(nlat=s[0], nlon=s[1], lmax=s[2], mmax=s[3], grid=s[4], batch=s[5], channels=s[6])
+                     for s in BATCH_MIX])
+    u, a, parts = _batched_io(pkg, plan, BATCH_MIX, seed=21)
+    du, da = _to_dev(u, torch.float32), _to_dev(a, torch.complex64)
+    outs = [plan.sht(du).cpu().numpy(), plan.isht(da).cpu().numpy(), plan.sht_T(da).cpu().numpy(),
+            plan.isht_T(du).cpu().numpy()]
+    for i, (shape, (go, so, ui, ai)) in enumerate(zip(BATCH_MIX, parts)):
+        nlat, nlon, lmax, mmax, grid, B, C = shape
+        _say("  segment", i, shape)
+        ng, ns = ui.size, ai.size
+        y = outs[0][so:so + ns].reshape(ai.shape)
+        x = outs[1][go:go + ng].reshape(ui.shape)
+        gx = outs[2][go:go + ng].reshape(ui.shape)
+        gy = outs[3][so:so + ns].reshape(ai.shape)
+        u64, a64 = ui.astype(np.float64), ai.astype(np.complex128)
+        errs = (rel_l2(y, oracle.sht(u64, lmax, mmax, grid)), rel_l2(x, oracle.isht(a64, nlat, nlon, grid)),
+                rel_l2(gx, oracle.sht_T(a64, nlat, nlon, grid)), rel_l2(gy, oracle.isht_T(u64, lmax, mmax, grid)))
+        _say("    rel-L2 sht/isht/sht_T/isht_T:", errs)
+        assert max(errs) <= TOL, (shape, errs)
+        single = _plan(pkg, *shape)
+        dui, dai = _to_dev(ui, torch.float32), _to_dev(ai, torch.complex64)
+        for got, ref in ((y, single.sht(dui)), (x, single.isht(dai)), (gx, single.sht_T(dai)),
+                         (gy, single.isht_T(dui))):
+            assert np.array_equal(got, ref.cpu().numpy()), shape
+        single.close()
+    plan.close()
