@@ -101,7 +101,8 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc,
                     sht_precision prec, void* hip_stream);
 
 /* Synchronise the plan's stream and free everything the plan owns.
- * NULL is accepted and ignored. */
+ * NULL is accepted and ignored.  SHT_ERR_INVALID_ARG (nothing freed) while
+ * graphs of the plan (sht_graph_create) still exist. */
 sht_status sht_plan_destroy(sht_plan_t plan);
 
 /* Element offsets of segment i inside the concatenated grid buffer (float32
@@ -160,6 +161,46 @@ sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void*
 #define SHT_TIMING_KINDS 6
 sht_status sht_plan_timing(sht_plan_t plan, int enable);
 sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds);
+
+/* Captured sequences (the batching form's replay path).  sht_graph_create
+ * records nops transforms of the plan -- ops[i] = SHT_OP_*, reading
+ * inputs[i] and writing outputs[i] (device buffers with the layouts of the
+ * corresponding entry points, owned by the caller and kept alive and in
+ * place while the graph exists) -- into a HIP graph by stream capture on a
+ * stream of the library's own, and instantiates it.  Nothing is launched
+ * at creation.  sht_graph_launch enqueues one replay of the whole sequence
+ * on hip_stream (NULL: the plan's stream) and returns without waiting;
+ * replays on one plan must not overlap in time (they share the plan's
+ * workspace).  Kernel timing is not recorded inside graphs.  The graph
+ * refers to the plan: destroy every graph before its plan.  The captured
+ * work allocates nothing and contains no memset nodes.
+ * Errors: SHT_ERR_INVALID_ARG (NULL plan/graph/arrays/buffers, nops outside
+ * [1, 64], unknown op, an input equal to its output), SHT_ERR_HIP (capture
+ * or instantiation failed). */
+typedef struct sht_graph_s* sht_graph_t;
+typedef enum { SHT_OP_SHT = 0, SHT_OP_ISHT = 1, SHT_OP_SHT_T = 2, SHT_OP_ISHT_T = 3 } sht_op;
+sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const void* const* inputs,
+                            void* const* outputs, sht_graph_t* out);
+sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream);
+sht_status sht_graph_destroy(sht_graph_t graph);
+
+/* Autotuner.  The work decomposition of a plan has free parameters that do
+ * not change any result bit: the orders per scheduling chunk of the
+ * Legendre work list (4, 8, 16, 32), how chunks are dealt to the 8 XCDs
+ * (largest-first to the least-loaded XCD, or round robin) and, for the
+ * bf16 forms, the field groups per workgroup (1 or 2).  sht_plan_tune
+ * times one SHT -> ISHT -> ISHT^T -> SHT^T pass per candidate (after one
+ * warm-up pass) on library-allocated synthetic buffers, requires every
+ * candidate's four outputs to equal the default candidate's bit for bit
+ * (parity), keeps the fastest, and returns its index in *chosen and its
+ * time in *best_ms (either may be NULL).  With cache_path != NULL the
+ * choice is looked up first in that text file under a key of (gfx arch,
+ * descriptors, precision) and appended to it after a measurement; a cached
+ * choice is applied without timing (*best_ms = -1).  Synchronises the
+ * plan's stream.  Errors: SHT_ERR_INVALID_ARG (NULL plan),
+ * SHT_ERR_OUT_OF_MEMORY, SHT_ERR_HIP, SHT_ERR_INTERNAL (a candidate's
+ * outputs differ from the default's). */
+sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, double* best_ms);
 
 const char* sht_status_string(sht_status s);
 const char* sht_last_error(void);

@@ -130,6 +130,20 @@ class Plan:
                                                1 if adjoint else 0, _stream_ptr(self.device)))
         return out
 
+    # ----------------------------------------------------- batching helpers
+    def tune(self, cache=None):
+        """Autotune the work schedule (sht_plan_tune); returns (candidate, ms),
+        ms = -1.0 when the choice came from the cache file."""
+        chosen, ms = ctypes.c_int(), ctypes.c_double()
+        path = None if cache is None else str(cache).encode()
+        _lib.check(_lib.load().sht_plan_tune(self._h, path, ctypes.byref(chosen), ctypes.byref(ms)))
+        return chosen.value, ms.value
+
+    def graph(self, ops):
+        """Capture a sequence [(op, input, output), ...] (op in "sht", "isht",
+        "sht_T", "isht_T") into a replayable HIP graph (sht_graph_create)."""
+        return Graph(self, ops)
+
     # ------------------------------------------------------------ diagnostics
     def set_timing(self, enable):
         """Record HIP events around every kernel launch of later calls."""
@@ -145,8 +159,9 @@ class Plan:
 
     # --------------------------------------------------------------- lifetime
     def close(self):
+        """Free the plan (raises ShtError while graphs of the plan exist)."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.load().sht_plan_destroy(self._h)
+            _lib.check(_lib.load().sht_plan_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -196,3 +211,48 @@ class ChannelMix(torch.autograd.Function):
     def backward(ctx, g):
         (W,) = ctx.saved_tensors
         return ctx.plan.mix(W, g.contiguous(), adjoint=True), None, None
+
+
+class Graph:
+    """A captured sequence of transforms on fixed buffers (sht_graph_*).  The
+    tensors stay referenced by the graph; replay with launch()."""
+
+    def __init__(self, plan, ops):
+        lib = _lib.load()
+        shapes = {"sht": ((torch.float32, plan.grid_shape()), (torch.complex64, plan.spec_shape())),
+                  "isht": ((torch.complex64, plan.spec_shape()), (torch.float32, plan.grid_shape())),
+                  "sht_T": ((torch.complex64, plan.spec_shape()), (torch.float32, plan.grid_shape())),
+                  "isht_T": ((torch.float32, plan.grid_shape()), (torch.complex64, plan.spec_shape()))}
+        n = len(ops)
+        codes = (ctypes.c_int * n)()
+        ins = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        self._keep = []
+        for i, (op, src, dst) in enumerate(ops):
+            if op not in _lib.OPS:
+                raise ValueError(f"unknown op {op!r}")
+            (sdt, sshape), (ddt, dshape) = shapes[op]
+            plan._check(src, sdt, sshape, "input")
+            plan._check(dst, ddt, dshape, "output")
+            codes[i] = _lib.OPS[op]
+            ins[i] = src.data_ptr()
+            outs[i] = dst.data_ptr()
+            self._keep += [src, dst]
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(plan.device):
+            _lib.check(lib.sht_graph_create(plan._h, n, codes, ins, outs, ctypes.byref(self._h)))
+
+    def launch(self):
+        _lib.check(_lib.load().sht_graph_launch(self._h, _stream_ptr(self.plan.device)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().sht_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

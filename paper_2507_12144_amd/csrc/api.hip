@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
 #include <cmath>
 #include <new>
 #include <cstdarg>
@@ -146,6 +147,17 @@ struct sht_plan_s {
   sht::SegDev* d_segs = nullptr;
   int2* bwork = nullptr;
   sht::BatchArgs batch{};
+  // schedule (sht_plan_tune): orders per chunk, XCD dealing policy, bf16
+  // field groups per workgroup (0: automatic)
+  int tune_chunk = 16, tune_policy = 0, tune_ncb = 0;
+  int graphs = 0;  // live sht_graph_t objects of this plan
+};
+
+struct sht_graph_s {
+  sht_plan_s* plan = nullptr;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace sht {
@@ -162,6 +174,28 @@ void free_segment(Segment& s) {
 __global__ void ring_scale_kernel(int nk, int nlon, const double* __restrict__ w, float* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nk) out[k] = static_cast<float>(2.0 * 3.14159265358979323846 / nlon * w[k]);
+}
+
+// Synthetic tuning input: a hash of the index mapped to [-1, 1).
+__global__ void tune_fill_kernel(float* __restrict__ p, size_t n, unsigned seed) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    unsigned h = static_cast<unsigned>(i) * 2654435761u ^ (static_cast<unsigned>(i >> 32) + seed) * 2246822519u;
+    h ^= h >> 15;
+    h *= 3266489917u;
+    h ^= h >> 13;
+    p[i] = static_cast<float>(h >> 8) * (2.0f / 16777216.0f) - 1.0f;
+  }
+}
+
+// Number of 32-bit words that differ between a and b, added to *count.
+__global__ void tune_compare_kernel(const unsigned* __restrict__ a, const unsigned* __restrict__ b, size_t n,
+                                    unsigned long long* __restrict__ count) {
+  unsigned long long c = 0;
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    c += a[i] != b[i];
+  if (c) atomicAdd(count, c);
 }
 
 template <typename T>
@@ -247,45 +281,6 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
     if (e != hipSuccess) return hip_fail(e, "Legendre table kernel");
   }
 
-  // contraction work list: the orders come in chunks of 16 consecutive m
-  // (whose 8-byte spectrum entries share 128-byte lines); chunks go to the 8
-  // XCDs largest first, each to the XCD with the least work so far, and each
-  // XCD processes its chunks in ascending m (largest items first).  The
-  // work of an item is taken as its number of 16-row blocks plus one.
-  {
-    const int chunks_per_m = (g.groups + S.ncb - 1) / S.ncb;
-    const int nq = (d.mmax + 15) / 16;
-    std::vector<int64_t> qwork(nq, 0);
-    for (int m = 0; m < d.mmax; ++m) qwork[m / 16] += static_cast<int64_t>(chunks_per_m) * ((((d.lmax - m + 1) >> 1) + 15) / 16 + 1);
-    std::vector<int> order(nq);
-    for (int q = 0; q < nq; ++q) order[q] = q;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return qwork[x] > qwork[y]; });
-    std::vector<std::vector<int>> xq(8);
-    std::vector<int64_t> load(8, 0);
-    for (int q : order) {
-      const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
-      xq[x].push_back(q);
-      load[x] += qwork[q];
-    }
-    std::vector<std::vector<int2>> slices(8);
-    for (int x = 0; x < 8; ++x) {
-      std::sort(xq[x].begin(), xq[x].end());
-      for (int q : xq[x])
-        for (int m = 16 * q; m < std::min(d.mmax, 16 * q + 16); ++m)
-          for (int c = 0; c < chunks_per_m; ++c) slices[x].push_back(make_int2(m, c));
-    }
-    size_t per = 1;
-    for (auto& v : slices) per = std::max(per, v.size());
-    std::vector<int2> flat;
-    flat.reserve(8 * per);
-    for (auto& v : slices) {
-      v.resize(per, make_int2(-1, -1));
-      flat.insert(flat.end(), v.begin(), v.end());
-    }
-    S.work_per = static_cast<int>(per);
-    if ((rc = upload(&S.worklist, flat, st, "work list")) != SHT_OK) return rc;
-  }
-
   // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
   const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.groups * g.kpad * 16 * sizeof(float);
   e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
@@ -297,37 +292,37 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   return SHT_OK;
 }
 
-// Plan-wide work list of the batched float32 Legendre kernels: items
-// {m, (segment << 16) | column chunk of kBatchNcb field groups}.  Orders come
-// in chunks of 16 consecutive m of one segment (their 8-byte spectrum
-// entries share 128-byte lines); chunks go to the 8 XCDs largest first, each
-// to the XCD with the least work so far (greedy LPT), and each XCD takes its
-// chunks largest first.  The work of an item is its number of 16-row blocks
-// plus one.
-std::vector<int2> batched_worklist(const std::vector<Segment>& segs, int chunk_m, size_t* per_out) {
-  struct Chunk {
-    int seg, m0, m1;
-    int64_t work;
-  };
-  std::vector<Chunk> chunks;
-  for (int si = 0; si < static_cast<int>(segs.size()); ++si) {
-    const sht_desc& d = segs[si].d;
-    const int cpm = (segs[si].g.groups + kBatchNcb - 1) / kBatchNcb;
-    for (int m0 = 0; m0 < d.mmax; m0 += chunk_m) {
-      Chunk c{si, m0, std::min(d.mmax, m0 + chunk_m), 0};
-      for (int m = c.m0; m < c.m1; ++m) c.work += static_cast<int64_t>(cpm) * ((((d.lmax - m + 1) >> 1) + 15) / 16 + 1);
-      chunks.push_back(c);
-    }
+// Work-list scheduling.  The orders of a segment come in chunks of
+// chunk_m consecutive m (whose 8-byte spectrum entries share 128-byte
+// lines).  Chunks are taken largest first and dealt to the 8 XCDs, either
+// each to the XCD with the least work so far (policy 0, greedy LPT) or round
+// robin (policy 1); each XCD runs its chunks largest first.  The work of an
+// item is its number of 16-row blocks plus one.  Items: {m, tag | column
+// chunk} with cpm column chunks per order.
+struct WorkChunk {
+  int m0, m1, cpm, tag;
+  int64_t work;
+};
+
+void add_chunks(std::vector<WorkChunk>* out, const sht_desc& d, int cpm, int tag, int chunk_m) {
+  for (int m0 = 0; m0 < d.mmax; m0 += chunk_m) {
+    WorkChunk c{m0, std::min(d.mmax, m0 + chunk_m), cpm, tag, 0};
+    for (int m = c.m0; m < c.m1; ++m) c.work += static_cast<int64_t>(cpm) * ((((d.lmax - m + 1) >> 1) + 15) / 16 + 1);
+    out->push_back(c);
   }
-  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& a, const Chunk& b) { return a.work > b.work; });
+}
+
+std::vector<int2> deal_chunks(std::vector<WorkChunk> chunks, int policy, size_t* per_out) {
+  std::stable_sort(chunks.begin(), chunks.end(),
+                   [](const WorkChunk& a, const WorkChunk& b) { return a.work > b.work; });
   std::vector<std::vector<int2>> slices(8);
   std::vector<int64_t> load(8, 0);
-  for (const Chunk& c : chunks) {
-    const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+  int rr = 0;
+  for (const WorkChunk& c : chunks) {
+    const int x = policy == 1 ? (rr++ % 8) : static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
     load[x] += c.work;
-    const int cpm = (segs[c.seg].g.groups + kBatchNcb - 1) / kBatchNcb;
     for (int m = c.m0; m < c.m1; ++m)
-      for (int k = 0; k < cpm; ++k) slices[x].push_back(make_int2(m, (c.seg << 16) | k));
+      for (int k = 0; k < c.cpm; ++k) slices[x].push_back(make_int2(m, c.tag | k));
   }
   size_t per = 1;
   for (auto& v : slices) per = std::max(per, v.size());
@@ -341,9 +336,46 @@ std::vector<int2> batched_worklist(const std::vector<Segment>& segs, int chunk_m
   return flat;
 }
 
-// Device segment table, DFT item numbering and (float32) the batched
-// Legendre work list of a plan whose segments are built.
-sht_status build_batch(sht_plan_s* p, int chunk_m) {
+// Work lists of a plan under its schedule (tune_chunk, tune_policy,
+// tune_ncb): the plan-wide list of the batched float32 Legendre kernels, or
+// the per-segment lists of the bf16 kernels.
+sht_status apply_schedule(sht_plan_s* p) {
+  sht_status rc = SHT_OK;
+  if (p->storage == Storage::F32) {
+    std::vector<WorkChunk> chunks;
+    for (size_t i = 0; i < p->segs.size(); ++i)
+      add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + kBatchNcb - 1) / kBatchNcb, static_cast<int>(i) << 16,
+                 p->tune_chunk);
+    size_t per = 0;
+    std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
+    if (p->bwork) {
+      (void)hipFree(p->bwork);
+      p->bwork = nullptr;
+    }
+    if ((rc = upload(&p->bwork, flat, p->stream, "batched work list")) != SHT_OK) return rc;
+    p->batch.work = p->bwork;
+    p->batch.work_per = static_cast<int>(per);
+    return SHT_OK;
+  }
+  for (Segment& S : p->segs) {
+    S.ncb = p->tune_ncb > 0 ? p->tune_ncb : legendre_ncb(S.g.groups);
+    std::vector<WorkChunk> chunks;
+    add_chunks(&chunks, S.d, (S.g.groups + S.ncb - 1) / S.ncb, 0, p->tune_chunk);
+    size_t per = 0;
+    std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
+    if (S.worklist) {
+      (void)hipFree(S.worklist);
+      S.worklist = nullptr;
+    }
+    if ((rc = upload(&S.worklist, flat, p->stream, "work list")) != SHT_OK) return rc;
+    S.work_per = static_cast<int>(per);
+  }
+  return SHT_OK;
+}
+
+// Device segment table, DFT item numbering and work lists of a plan whose
+// segments are built.
+sht_status build_batch(sht_plan_s* p) {
   std::vector<SegDev> h(p->segs.size());
   int items = 0;
   size_t lds = 0;
@@ -367,28 +399,15 @@ sht_status build_batch(sht_plan_s* p, int chunk_m) {
     items += d.dft_items;
     lds = std::max(lds, dft_lds_bytes(S.g.nlon));
   }
-  if (p->d_segs) {
-    (void)hipFree(p->d_segs);
-    p->d_segs = nullptr;
-  }
   sht_status rc = upload(&p->d_segs, h, p->stream, "segment table");
   if (rc != SHT_OK) return rc;
   p->batch.segs = p->d_segs;
   p->batch.nseg = static_cast<int>(h.size());
   p->batch.dft_total = items;
   p->batch.dft_lds = lds;
-  if (p->storage == Storage::F32) {
-    size_t per = 0;
-    std::vector<int2> flat = batched_worklist(p->segs, chunk_m, &per);
-    if (p->bwork) {
-      (void)hipFree(p->bwork);
-      p->bwork = nullptr;
-    }
-    if ((rc = upload(&p->bwork, flat, p->stream, "batched work list")) != SHT_OK) return rc;
-    p->batch.work = p->bwork;
-    p->batch.work_per = static_cast<int>(per);
-  }
-  return SHT_OK;
+  hipError_t e = prepare_dft_kernels(lds);
+  if (e != hipSuccess) return hip_fail(e, "ring DFT kernel attributes");
+  return apply_schedule(p);
 }
 
 LegArgs leg_args(const Segment& S) {
@@ -544,7 +563,7 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
   }
   p->grid_elems = goff;
   p->spec_elems = soff;
-  sht_status rc = build_batch(p, 16);
+  sht_status rc = build_batch(p);
   if (rc != SHT_OK) {
     for (Segment& T : p->segs) free_segment(T);
     if (p->d_segs) (void)hipFree(p->d_segs);
@@ -558,6 +577,7 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
 
 sht_status sht_plan_destroy(sht_plan_t plan) {
   if (!plan) return SHT_OK;
+  if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs first");
   sht_status rc = SHT_OK;
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
@@ -624,6 +644,243 @@ sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void*
                               static_cast<const float2*>(in), static_cast<float2*>(out), adjoint, st);
   });
   if (e != hipSuccess) return hip_fail(e, "channel mix launch");
+  return SHT_OK;
+}
+
+sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const void* const* inputs,
+                            void* const* outputs, sht_graph_t* out) {
+  if (!out) return fail(SHT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!plan || !ops || !inputs || !outputs) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (nops < 1 || nops > 64) return fail(SHT_ERR_INVALID_ARG, "nops must be in [1, 64]");
+  for (int i = 0; i < nops; ++i) {
+    if (ops[i] < SHT_OP_SHT || ops[i] > SHT_OP_ISHT_T) return fail(SHT_ERR_INVALID_ARG, "op %d: unknown op", i);
+    if (!inputs[i] || !outputs[i]) return fail(SHT_ERR_INVALID_ARG, "op %d: NULL buffer", i);
+    if (inputs[i] == outputs[i]) return fail(SHT_ERR_INVALID_ARG, "op %d: input equals output", i);
+  }
+  auto* g = new (std::nothrow) sht_graph_s();
+  if (!g) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
+  g->plan = plan;
+  auto cleanup = [&](sht_status rc) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->capture) (void)hipStreamDestroy(g->capture);
+    delete g;
+    return rc;
+  };
+  hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "capture stream"));
+  // the captured work must not depend on earlier work of the plan's stream
+  e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamSynchronize"));
+  const bool timing = plan->timing;
+  plan->timing = false;
+  e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    plan->timing = timing;
+    return cleanup(hip_fail(e, "hipStreamBeginCapture"));
+  }
+  sht_status rc = SHT_OK;
+  for (int i = 0; i < nops && rc == SHT_OK; ++i) {
+    const Op op = ops[i] == SHT_OP_SHT ? Op::SHT : ops[i] == SHT_OP_ISHT ? Op::ISHT
+                  : ops[i] == SHT_OP_SHT_T ? Op::SHT_T : Op::ISHT_T;
+    rc = run(plan, op, inputs[i], outputs[i], g->capture);
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(g->capture, &graph);
+  plan->timing = timing;
+  g->graph = graph;
+  if (rc != SHT_OK) return cleanup(rc);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamEndCapture"));
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipGraphInstantiate"));
+  plan->graphs += 1;
+  *out = g;
+  return SHT_OK;
+}
+
+sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream) {
+  if (!graph) return fail(SHT_ERR_INVALID_ARG, "graph is NULL");
+  hipError_t e = hipGraphLaunch(graph->exec, pick_stream(graph->plan, hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SHT_OK;
+}
+
+sht_status sht_graph_destroy(sht_graph_t graph) {
+  if (!graph) return SHT_OK;
+  sht_status rc = SHT_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  if (graph->capture) (void)hipStreamDestroy(graph->capture);
+  graph->plan->graphs -= 1;
+  delete graph;
+  return rc;
+}
+
+sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, double* best_ms) {
+  if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs before tuning it");
+  struct Cand {
+    int chunk, policy, ncb;
+  };
+  std::vector<Cand> cands = {{16, 0, 0}, {4, 0, 0}, {8, 0, 0}, {32, 0, 0}, {16, 1, 0}, {8, 1, 0}};
+  if (plan->storage != Storage::F32) {
+    cands.push_back({16, 0, 1});
+    cands.push_back({16, 0, 2});
+  }
+  auto apply = [&](const Cand& c) {
+    plan->tune_chunk = c.chunk;
+    plan->tune_policy = c.policy;
+    plan->tune_ncb = c.ncb;
+    return apply_schedule(plan);
+  };
+  // cache key: arch | descriptors | precision
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, plan->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  std::string key = std::string(prop.gcnArchName) + "|";
+  for (const Segment& S : plan->segs) {
+    char buf[128];
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d;", S.d.nlat, S.d.nlon, S.d.lmax, S.d.mmax,
+             static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
+    key += buf;
+  }
+  key += "|" + std::to_string(static_cast<int>(plan->prec));
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    int found = -1;
+    while (std::getline(in, line)) {
+      const size_t tab = line.rfind('\t');
+      if (tab != std::string::npos && line.compare(0, tab, key) == 0) found = std::atoi(line.c_str() + tab + 1);
+    }
+    if (found >= 0 && found < static_cast<int>(cands.size())) {
+      sht_status rc = apply(cands[found]);
+      if (rc != SHT_OK) return rc;
+      if (chosen) *chosen = found;
+      if (best_ms) *best_ms = -1.0;
+      return SHT_OK;
+    }
+  }
+  // buffers: inputs u (grid), a (spectrum); outputs and the default's copies
+  const size_t ng = plan->grid_elems, ns = 2 * plan->spec_elems;  // floats
+  float* buf[10] = {};
+  const size_t sizes[10] = {ng, ns, ns, ng, ns, ng, ns, ng, ns, ng};
+  unsigned long long* count = nullptr;
+  auto release = [&]() {
+    for (float* b : buf)
+      if (b) (void)hipFree(b);
+    if (count) (void)hipFree(count);
+  };
+  for (int i = 0; i < 10; ++i) {
+    e = dev_alloc(reinterpret_cast<void**>(&buf[i]), sizes[i] * sizeof(float));
+    if (e != hipSuccess) {
+      release();
+      return hip_fail(e, "tuning buffers");
+    }
+  }
+  e = dev_alloc(reinterpret_cast<void**>(&count), sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    release();
+    return hip_fail(e, "tuning buffers");
+  }
+  hipStream_t st = plan->stream;
+  // the gaps between segments are never written: clear them in every buffer
+  for (int i = 0; i < 10; ++i) {
+    e = hipMemsetAsync(buf[i], 0, sizes[i] * sizeof(float), st);
+    if (e != hipSuccess) {
+      release();
+      return hip_fail(e, "tuning buffers");
+    }
+  }
+  hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, st, buf[0], ng, 1u);
+  hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, st, buf[1], ns, 2u);
+  // one pass: y = SHT u, x = ISHT a, gy = ISHT^T u, gx = SHT^T a
+  auto pass = [&](float* y, float* x, float* gy, float* gx) {
+    sht_status rc = run(plan, Op::SHT, buf[0], y, st);
+    if (rc == SHT_OK) rc = run(plan, Op::ISHT, buf[1], x, st);
+    if (rc == SHT_OK) rc = run(plan, Op::ISHT_T, buf[0], gy, st);
+    if (rc == SHT_OK) rc = run(plan, Op::SHT_T, buf[1], gx, st);
+    return rc;
+  };
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  (void)hipEventCreate(&ev0);
+  (void)hipEventCreate(&ev1);
+  const bool timing = plan->timing;
+  plan->timing = false;
+  sht_status rc = SHT_OK;
+  int best = 0;
+  float best_t = 0.f;
+  const Cand saved{plan->tune_chunk, plan->tune_policy, plan->tune_ncb};
+  for (size_t ci = 0; ci < cands.size() && rc == SHT_OK; ++ci) {
+    rc = apply(cands[ci]);
+    if (rc != SHT_OK) break;
+    float* o[4] = {buf[2], buf[3], buf[4], buf[5]};
+    if (ci == 0) {
+      o[0] = buf[6];
+      o[1] = buf[7];
+      o[2] = buf[8];
+      o[3] = buf[9];
+    }
+    rc = pass(o[0], o[1], o[2], o[3]);  // warm-up
+    if (rc != SHT_OK) break;
+    (void)hipEventRecord(ev0, st);
+    rc = pass(o[0], o[1], o[2], o[3]);
+    (void)hipEventRecord(ev1, st);
+    if (rc != SHT_OK) break;
+    e = hipEventSynchronize(ev1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev0, ev1);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "tuning timing");
+      break;
+    }
+    if (ci > 0) {  // parity: bit-identical to the default candidate
+      e = hipMemsetAsync(count, 0, sizeof(unsigned long long), st);
+      for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+        hipLaunchKernelGGL(tune_compare_kernel, dim3(1024), dim3(256), 0, st,
+                           reinterpret_cast<const unsigned*>(o[k]), reinterpret_cast<const unsigned*>(buf[6 + k]),
+                           sizes[2 + k], count);
+        e = hipGetLastError();
+      }
+      unsigned long long diff = 0;
+      if (e == hipSuccess) e = hipMemcpy(&diff, count, sizeof(diff), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "tuning parity check");
+        break;
+      }
+      if (diff != 0) {
+        rc = fail(SHT_ERR_INTERNAL, "tuning candidate %zu differs from the default in %llu words", ci, diff);
+        break;
+      }
+    }
+    if (ci == 0 || t < best_t) {
+      best = static_cast<int>(ci);
+      best_t = t;
+    }
+  }
+  plan->timing = timing;
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipStreamSynchronize(st);
+  release();
+  if (rc != SHT_OK) {
+    plan->tune_chunk = saved.chunk;
+    plan->tune_policy = saved.policy;
+    plan->tune_ncb = saved.ncb;
+    (void)apply_schedule(plan);
+    return rc;
+  }
+  rc = apply(cands[best]);
+  if (rc != SHT_OK) return rc;
+  if (cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    if (outf) outf << key << '\t' << best << '\n';
+  }
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = best_t;
   return SHT_OK;
 }
 

@@ -618,9 +618,13 @@ size_t dft_lds_bytes(int nlon) {
   }
 }
 
+hipError_t prepare_dft_kernels(size_t lds_bytes) {
+  hipError_t e = prepare_lds(reinterpret_cast<const void*>(dft_forward_batched), lds_bytes);
+  if (e == hipSuccess) e = prepare_lds(reinterpret_cast<const void*>(dft_inverse_batched), lds_bytes);
+  return e;
+}
+
 hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool sht_scale, hipStream_t st) {
-  hipError_t e = prepare_lds(reinterpret_cast<const void*>(dft_forward_batched), b.dft_lds);
-  if (e != hipSuccess) return e;
   const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
   hipLaunchKernelGGL(dft_forward_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x,
                      sht_scale ? 1 : 0);
@@ -628,8 +632,6 @@ hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool s
 }
 
 hipError_t launch_dft_inverse_batched(const BatchArgs& b, float* x, bool sht_scale, float c_rest, hipStream_t st) {
-  hipError_t e = prepare_lds(reinterpret_cast<const void*>(dft_inverse_batched), b.dft_lds);
-  if (e != hipSuccess) return e;
   const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
   hipLaunchKernelGGL(dft_inverse_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x,
                      sht_scale ? 1 : 0, c_rest);

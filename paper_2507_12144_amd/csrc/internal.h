@@ -80,8 +80,11 @@ struct BatchArgs {
 };
 // Field groups per column chunk of the batched float32 Legendre kernels.
 constexpr int kBatchNcb = 2;
-// Dynamic LDS the DFT kernels need for ring width nlon.
+// Dynamic LDS the DFT kernels need for ring width nlon; prepare_dft_kernels
+// raises the batched kernels' dynamic-LDS limit to lds_bytes (call once per
+// plan, outside any stream capture).
 size_t dft_lds_bytes(int nlon);
+hipError_t prepare_dft_kernels(size_t lds_bytes);
 // Forward ring DFT of every segment's ring pairs (k, nlat-1-k), k < nk,
 // multiplied by the ring scale (sht_scale: (2 pi / nlon) w_k, else 1),
 // folded into symmetric/antisymmetric parts and written to the segment's

@@ -399,3 +399,82 @@ def test_batched_uneven_segments(pkg):
             assert np.array_equal(got, ref.cpu().numpy()), shape
         single.close()
     plan.close()
+
+
+GRAPH_SEGS = [(33, 64, 17, 17, 0, 1, 3), (181, 360, 180, 180, 0, 2, 3), (32, 64, 32, 32, 1, 1, 2)]
+
+
+def _multi_plan(P, shapes, precision="fp32"):
+    return P.Plan([dict(nlat=s[0], nlon=s[1], lmax=s[2], mmax=s[3], grid=s[4], batch=s[5], channels=s[6])
+                   for s in shapes], precision=precision)
+
+
+def _segment_mask(plan, shapes, spectral):
+    """True on the entries of the segments (the alignment gaps between
+    segments are never written)."""
+    n = plan.spec_elems if spectral else plan.grid_elems
+    mask = np.zeros(n, bool)
+    for i, (nlat, nlon, lmax, mmax, grid, B, C) in enumerate(shapes):
+        go, so = plan.segment(i)
+        off, size = (so, B * C * lmax * mmax) if spectral else (go, B * C * nlat * nlon)
+        mask[off:off + size] = True
+    return mask
+
+
+def test_graph_replay_matches_eager(pkg):
+    """The fwd+bwd chain SHT -> ISHT -> ISHT^T -> SHT^T captured as one HIP
+    graph; several replays, with eager work and synchronisation between them,
+    each equal bit for bit to the eager chain."""
+    _say("graph replay over", GRAPH_SEGS)
+    plan = _multi_plan(pkg, GRAPH_SEGS)
+    u_h, _, _ = _batched_io(pkg, plan, GRAPH_SEGS, seed=5)
+    u = _to_dev(u_h, torch.float32)
+    y = plan.sht(u)
+    x = plan.isht(y)
+    gy = plan.isht_T(x)
+    gx = plan.sht_T(gy)
+    ref = [t.cpu().numpy() for t in (y, x, gy, gx)]
+    ys, xs, gys, gxs = (torch.empty_like(t) for t in (y, x, gy, gx))
+    g = plan.graph([("sht", u, ys), ("isht", ys, xs), ("isht_T", xs, gys), ("sht_T", gys, gxs)])
+    other = torch.randn_like(u)
+    masks = [_segment_mask(plan, GRAPH_SEGS, sp) for sp in (True, False, True, False)]
+    for rep in range(4):
+        for t in (ys, xs, gys, gxs):
+            t.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        for got, r, mk in zip((ys, xs, gys, gxs), ref, masks):
+            assert np.array_equal(got.cpu().numpy()[mk], r[mk]), rep
+        plan.sht(other)          # eager work on the same plan between replays
+        (other * 2).sum().item()
+        torch.cuda.synchronize()
+    with pytest.raises(pkg.ShtError):
+        plan.close()             # graphs must go first
+    g.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_tune_parity_and_cache(pkg, tmp_path, prec):
+    """Every tuning candidate must reproduce the default schedule's outputs
+    bit for bit (checked inside sht_plan_tune); the chosen schedule gives the
+    same outputs as before tuning, and the cached choice is reused."""
+    _say("tune", prec)
+    plan = _multi_plan(pkg, GRAPH_SEGS, prec)
+    u_h, a_h, _ = _batched_io(pkg, plan, GRAPH_SEGS, seed=9)
+    u, a = _to_dev(u_h, torch.float32), _to_dev(a_h, torch.complex64)
+    before = [plan.sht(u).cpu().numpy(), plan.isht(a).cpu().numpy()]
+    cache = tmp_path / "tune.txt"
+    choice, ms = plan.tune(cache)
+    _say("  chosen", choice, "ms", ms)
+    assert ms > 0
+    after = [plan.sht(u).cpu().numpy(), plan.isht(a).cpu().numpy()]
+    masks = [_segment_mask(plan, GRAPH_SEGS, True), _segment_mask(plan, GRAPH_SEGS, False)]
+    for b, c, mk in zip(before, after, masks):
+        assert np.array_equal(b[mk], c[mk])
+    plan2 = _multi_plan(pkg, GRAPH_SEGS, prec)
+    choice2, ms2 = plan2.tune(cache)
+    assert (choice2, ms2) == (choice, -1.0)
+    assert np.array_equal(plan2.sht(u).cpu().numpy()[masks[0]], before[0][masks[0]])
+    plan.close()
+    plan2.close()
