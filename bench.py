@@ -40,6 +40,10 @@ def parse():
                     help="only copy a 256 MiB device buffer three times (reference kernel for HBM counters)")
     ap.add_argument("--cpu-fields", type=int, default=72,
                     help="fields in the oracle's timed sample (of the 72)")
+    ap.add_argument("--workload", default="sht721", choices=["sht721", "batched"],
+                    help="sht721: the headline single-grid step; batched: uneven grids in one plan, "
+                         "graph-replayed, with p50/p99 replay latency")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batched workload)")
     return ap.parse_args()
 
 
@@ -92,10 +96,86 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 3}), flush=True)
 
 
+# 16 ensemble members over three equiangular grids (poles included,
+# Clenshaw-Curtis weights), 72 channels each
+BATCHED_SEGMENTS = [  # nlat, nlon, lmax, members
+    (181, 360, 180, 5),
+    (361, 720, 360, 5),
+    (721, 1440, 720, 6),
+]
+
+
+def batched_bench(args):
+    """One plan over the three grids; the fwd+bwd chain SHT -> ISHT -> ISHT^T
+    -> SHT^T over all 16 x 72 fields captured as one HIP graph after the
+    schedule autotuner ran; each replay timed with HIP events."""
+    import numpy as np
+    import torch
+    import paper_2507_12144_amd as P
+    torch.cuda.set_device(0)
+    C = 72
+    descs = [dict(nlat=a, nlon=b, lmax=L, mmax=L, grid="equiangular", batch=B, channels=C)
+             for a, b, L, B in BATCHED_SEGMENTS]
+    fields = sum(B for *_, B in BATCHED_SEGMENTS) * C
+    t0 = time.perf_counter()
+    plan = P.Plan(descs, precision=args.precision)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    choice, tune_ms = plan.tune(args.tune_cache)
+    tune_s = time.perf_counter() - t0
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    u = torch.randn(plan.grid_shape(), device="cuda", generator=gen)
+    y = torch.empty(plan.spec_shape(), dtype=torch.complex64, device="cuda")
+    x = torch.empty(plan.grid_shape(), dtype=torch.float32, device="cuda")
+    gy, gx = torch.empty_like(y), torch.empty_like(x)
+    graph = plan.graph([("sht", u, y), ("isht", y, x), ("isht_T", x, gy), ("sht_T", gy, gx)])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        graph.launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        graph.launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    out = {
+        "metric": "batched uneven-grid SHT+ISHT fwd+bwd fields/sec (one plan, graph replay); p50/p99 replay latency",
+        "value": round(fields * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": "16 ensemble members x 72 channels over equiangular 181x360 (L180), 361x720 "
+                               "(L360) and 721x1440 (L720) grids in one plan; SHT->ISHT->ISHT^T->SHT^T "
+                               "captured as one HIP graph",
+                   "segments": [dict(nlat=a, nlon=b, lmax=L, members=B, channels=C) for a, b, L, B in
+                                BATCHED_SEGMENTS],
+                   "fields": fields, "precision": args.precision},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                       "min": round(float(lat.min()), 4), "max": round(float(lat.max()), 4)},
+        "tuner": {"chosen": choice, "best_pass_ms": round(tune_ms, 3), "seconds": round(tune_s, 2)},
+        "plan_build_s": round(plan_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+    graph.close()
+    plan.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "batched":
+        if args.gpus != 1:
+            print("bench.py: this build measures one GPU only", file=sys.stderr, flush=True)
+            sys.exit(2)
+        batched_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
