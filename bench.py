@@ -63,7 +63,7 @@ def profiled_traffic(kind, precision):
     has changed since the counters were taken."""
     import glob
     import hashlib
-    src_file = "legendre.hip" if precision == "fp32" else "legendre_bf16.hip"
+    src_file = "legendre.hip" if precision == "fp32" else "legendre_bf16.h"
     src_key = "legendre" if precision == "fp32" else "legendre_bf16"
     with open(os.path.join(ROOT, "paper_2507_12144_amd", "csrc", src_file), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()[:16]

@@ -53,7 +53,8 @@ typedef enum {
     SHT_OK = 0,
     SHT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, unknown enum        */
     SHT_ERR_UNSUPPORTED = 2,   /* valid but not implemented: a prime factor
-                                  > 5 in nlon, nlon > 2048, nlat > 768       */
+                                  > 5 in nlon, nlon > 2048, nlat > 768,
+                                  batch * channels > 2^20                    */
     SHT_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed                 */
     SHT_ERR_HIP = 4,           /* a HIP runtime call failed                  */
     SHT_ERR_INTERNAL = 5
@@ -186,9 +187,8 @@ sht_status sht_graph_destroy(sht_graph_t graph);
 
 /* Autotuner.  The work decomposition of a plan has free parameters that do
  * not change any result bit: the orders per scheduling chunk of the
- * Legendre work list (4, 8, 16, 32), how chunks are dealt to the 8 XCDs
- * (largest-first to the least-loaded XCD, or round robin) and, for the
- * bf16 forms, the field groups per workgroup (1 or 2).  sht_plan_tune
+ * Legendre work list (4, 8, 16, 32) and how chunks are dealt to the 8
+ * XCDs (largest-first to the least-loaded XCD, or round robin).  sht_plan_tune
  * times one SHT -> ISHT -> ISHT^T -> SHT^T pass per candidate (after one
  * warm-up pass) on library-allocated synthetic buffers, requires every
  * candidate's four outputs to equal the default candidate's bit for bit

@@ -96,9 +96,6 @@ struct Segment {
   void* tab_ana = nullptr;     // Legendre table, analysis fragment order
   void* tab_syn = nullptr;     // Legendre table, synthesis fragment order
   int64_t* tab_off = nullptr;  // [mmax]
-  int2* worklist = nullptr;
-  int work_per = 0;
-  int ncb = 1;
   float* work = nullptr;
 };
 
@@ -120,7 +117,8 @@ sht_status validate_desc(const sht_desc& d, int i) {
   if (!only_small_primes(d.nlon))
     return fail(SHT_ERR_UNSUPPORTED, "desc %d: nlon = %d has a prime factor > 5", i, d.nlon);
   const long long F = static_cast<long long>(d.batch) * d.channels;
-  if (F > (1LL << 24) || static_cast<long long>(d.nlat) > (1 << 20) || d.lmax > (1 << 16))
+  // work items carry the column chunk (16 fields) in 16 bits
+  if (F > (1LL << 20) || static_cast<long long>(d.nlat) > (1 << 20) || d.lmax > (1 << 16))
     return fail(SHT_ERR_UNSUPPORTED, "desc %d: sizes beyond the supported range", i);
   return SHT_OK;
 }
@@ -147,9 +145,8 @@ struct sht_plan_s {
   sht::SegDev* d_segs = nullptr;
   int2* bwork = nullptr;
   sht::BatchArgs batch{};
-  // schedule (sht_plan_tune): orders per chunk, XCD dealing policy, bf16
-  // field groups per workgroup (0: automatic)
-  int tune_chunk = 16, tune_policy = 0, tune_ncb = 0;
+  // schedule (sht_plan_tune): orders per chunk, XCD dealing policy
+  int tune_chunk = 16, tune_policy = 0;
   int graphs = 0;  // live sht_graph_t objects of this plan
 };
 
@@ -165,7 +162,7 @@ namespace {
 
 void free_segment(Segment& s) {
   void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.tab_ana, s.tab_syn, s.tab_off,
-                  s.worklist, s.work};
+                  s.work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = Segment{};
@@ -223,7 +220,6 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   g.kpad = legendre_ring_pad(g.nk);
   g.groups = (g.F + 7) / 8;
   if (g.kpad < 0) return fail(SHT_ERR_UNSUPPORTED, "nlat = %d: more than %d northern rings", d.nlat, kMaxRings);
-  S.ncb = legendre_ncb(g.groups);
   if (!make_dft_plan(d.nlon, &S.dp)) return fail(SHT_ERR_UNSUPPORTED, "nlon = %d cannot be factored", d.nlon);
 
   hipError_t e;
@@ -336,40 +332,23 @@ std::vector<int2> deal_chunks(std::vector<WorkChunk> chunks, int policy, size_t*
   return flat;
 }
 
-// Work lists of a plan under its schedule (tune_chunk, tune_policy,
-// tune_ncb): the plan-wide list of the batched float32 Legendre kernels, or
-// the per-segment lists of the bf16 kernels.
+// Plan-wide work list of the batched Legendre kernels under the plan's
+// schedule (tune_chunk, tune_policy).
 sht_status apply_schedule(sht_plan_s* p) {
-  sht_status rc = SHT_OK;
-  if (p->storage == Storage::F32) {
-    std::vector<WorkChunk> chunks;
-    for (size_t i = 0; i < p->segs.size(); ++i)
-      add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + kBatchNcb - 1) / kBatchNcb, static_cast<int>(i) << 16,
-                 p->tune_chunk);
-    size_t per = 0;
-    std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
-    if (p->bwork) {
-      (void)hipFree(p->bwork);
-      p->bwork = nullptr;
-    }
-    if ((rc = upload(&p->bwork, flat, p->stream, "batched work list")) != SHT_OK) return rc;
-    p->batch.work = p->bwork;
-    p->batch.work_per = static_cast<int>(per);
-    return SHT_OK;
+  std::vector<WorkChunk> chunks;
+  for (size_t i = 0; i < p->segs.size(); ++i)
+    add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + kBatchNcb - 1) / kBatchNcb, static_cast<int>(i) << 16,
+               p->tune_chunk);
+  size_t per = 0;
+  std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
+  if (p->bwork) {
+    (void)hipFree(p->bwork);
+    p->bwork = nullptr;
   }
-  for (Segment& S : p->segs) {
-    S.ncb = p->tune_ncb > 0 ? p->tune_ncb : legendre_ncb(S.g.groups);
-    std::vector<WorkChunk> chunks;
-    add_chunks(&chunks, S.d, (S.g.groups + S.ncb - 1) / S.ncb, 0, p->tune_chunk);
-    size_t per = 0;
-    std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
-    if (S.worklist) {
-      (void)hipFree(S.worklist);
-      S.worklist = nullptr;
-    }
-    if ((rc = upload(&S.worklist, flat, p->stream, "work list")) != SHT_OK) return rc;
-    S.work_per = static_cast<int>(per);
-  }
+  sht_status rc = upload(&p->bwork, flat, p->stream, "batched work list");
+  if (rc != SHT_OK) return rc;
+  p->batch.work = p->bwork;
+  p->batch.work_per = static_cast<int>(per);
   return SHT_OK;
 }
 
@@ -408,18 +387,6 @@ sht_status build_batch(sht_plan_s* p) {
   hipError_t e = prepare_dft_kernels(lds);
   if (e != hipSuccess) return hip_fail(e, "ring DFT kernel attributes");
   return apply_schedule(p);
-}
-
-LegArgs leg_args(const Segment& S) {
-  LegArgs a{};
-  a.g = S.g;
-  a.tab_ana = S.tab_ana;
-  a.tab_syn = S.tab_syn;
-  a.tab_off = S.tab_off;
-  a.work = S.worklist;
-  a.work_per = S.work_per;
-  a.ncb = S.ncb;
-  return a;
 }
 
 hipStream_t pick_stream(const sht_plan_s* p, void* s) {
@@ -471,23 +438,15 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
     e = hipSetDevice(plan->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   }
-  // One launch per stage covers every segment (float32); the bf16 forms
-  // run their Legendre step per segment.
+  // One launch per stage covers every segment of the plan.
   const int planes = storage_planes(plan->storage);
   const BatchArgs& B = plan->batch;
   auto legendre = [&](bool analysis, const void* src, void* dst, float c_rest) -> hipError_t {
     if (!planes)
       return analysis ? launch_legendre_analysis_batched(B, static_cast<float2*>(dst), c_rest, st)
                       : launch_legendre_synthesis_batched(B, static_cast<const float2*>(src), st);
-    for (Segment& S : plan->segs) {
-      hipError_t e2 =
-          analysis ? launch_legendre_analysis_bf16(leg_args(S), planes, S.work,
-                                                   static_cast<float2*>(dst) + S.spec_off, c_rest, st)
-                   : launch_legendre_synthesis_bf16(leg_args(S), planes, static_cast<const float2*>(src) + S.spec_off,
-                                                    S.work, st);
-      if (e2 != hipSuccess) return e2;
-    }
-    return hipSuccess;
+    return analysis ? launch_legendre_analysis_bf16_batched(B, planes, static_cast<float2*>(dst), c_rest, st)
+                    : launch_legendre_synthesis_bf16_batched(B, planes, static_cast<const float2*>(src), st);
   };
   switch (op) {
     case Op::SHT:
@@ -723,17 +682,12 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
   if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs before tuning it");
   struct Cand {
-    int chunk, policy, ncb;
+    int chunk, policy;
   };
-  std::vector<Cand> cands = {{16, 0, 0}, {4, 0, 0}, {8, 0, 0}, {32, 0, 0}, {16, 1, 0}, {8, 1, 0}};
-  if (plan->storage != Storage::F32) {
-    cands.push_back({16, 0, 1});
-    cands.push_back({16, 0, 2});
-  }
+  const std::vector<Cand> cands = {{16, 0}, {4, 0}, {8, 0}, {32, 0}, {16, 1}, {8, 1}};
   auto apply = [&](const Cand& c) {
     plan->tune_chunk = c.chunk;
     plan->tune_policy = c.policy;
-    plan->tune_ncb = c.ncb;
     return apply_schedule(plan);
   };
   // cache key: arch | descriptors | precision
@@ -813,7 +767,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   sht_status rc = SHT_OK;
   int best = 0;
   float best_t = 0.f;
-  const Cand saved{plan->tune_chunk, plan->tune_policy, plan->tune_ncb};
+  const Cand saved{plan->tune_chunk, plan->tune_policy};
   for (size_t ci = 0; ci < cands.size() && rc == SHT_OK; ++ci) {
     rc = apply(cands[ci]);
     if (rc != SHT_OK) break;
@@ -869,7 +823,6 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   if (rc != SHT_OK) {
     plan->tune_chunk = saved.chunk;
     plan->tune_policy = saved.policy;
-    plan->tune_ncb = saved.ncb;
     (void)apply_schedule(plan);
     return rc;
   }

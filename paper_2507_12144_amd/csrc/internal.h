@@ -78,7 +78,7 @@ struct BatchArgs {
   int dft_total;           // DFT items of all segments
   size_t dft_lds;          // dynamic LDS of the batched DFT kernels
 };
-// Field groups per column chunk of the batched float32 Legendre kernels.
+// Field groups per column chunk of the batched Legendre kernels.
 constexpr int kBatchNcb = 2;
 // Dynamic LDS the DFT kernels need for ring width nlon; prepare_dft_kernels
 // raises the batched kernels' dynamic-LDS limit to lds_bytes (call once per
@@ -102,28 +102,13 @@ hipError_t launch_legendre_analysis_batched(const BatchArgs& b, float2* y, float
 hipError_t launch_legendre_synthesis_batched(const BatchArgs& b, const float2* y, hipStream_t st);
 
 // ---- legendre.hip --------------------------------------------------------
-// Work lists: 8 slices (one per XCD) of work_per entries, padded with
-// {-1, -1}; items are {m, column chunk}.  ncb = field groups per column
-// chunk.
-struct LegArgs {
-  SegGeom g;
-  const void* tab_ana;     // Legendre table, analysis fragment order
-  const void* tab_syn;     // Legendre table, synthesis fragment order
-  const int64_t* tab_off;  // [mmax] first element of order m
-  const int2* work;
-  int work_per;
-  int ncb;
-};
 // Ring padding the contraction kernels support for nk rings (-1: none).
 int legendre_ring_pad(int nk);
-// Field groups per column chunk for a segment with `groups` groups.
-int legendre_ncb(int groups);
-// bf16 forms (legendre_bf16.hip), per segment, the contract of the batched
-// float32 steps with `planes` table planes.
-hipError_t launch_legendre_analysis_bf16(const LegArgs& a, int planes, const float* W, float2* y, float c_rest,
-                                         hipStream_t stream);
-hipError_t launch_legendre_synthesis_bf16(const LegArgs& a, int planes, const float2* y, float* W,
-                                          hipStream_t stream);
+// bf16 forms (legendre_bf16*.hip): the contract of the batched float32
+// steps, with the table stored as `planes` bf16 planes.
+hipError_t launch_legendre_analysis_bf16_batched(const BatchArgs& b, int planes, float2* y, float c_rest,
+                                                 hipStream_t st);
+hipError_t launch_legendre_synthesis_bf16_batched(const BatchArgs& b, int planes, const float2* y, hipStream_t st);
 
 // ---- mix.hip -------------------------------------------------------------
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace sht {
 
 // Work item of this workgroup.  The hardware deals workgroups to the 8 XCDs
@@ -54,6 +56,29 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
+}
+
+}  // namespace sht
+
+namespace sht {
+
+// Calls f(integral_constant<U>) for U = 0, 1, ..., END-1 as straight-line
+// code, stopping after the first call that returns false.
+template <int U, int END, class F>
+__device__ __forceinline__ bool unrolled(F&& f) {
+  if constexpr (U < END) {
+    if (!f(std::integral_constant<int, U>{})) return false;
+    return unrolled<U + 1, END>(f);
+  }
+  return true;
+}
+
+// LDS buffer of stage u of a ring of three.
+template <int U, class T>
+__device__ __forceinline__ T* ring_buf(T* b0, T* b1, T* b2) {
+  if constexpr (U % 3 == 0) return b0;
+  else if constexpr (U % 3 == 1) return b1;
+  else return b2;
 }
 
 }  // namespace sht

@@ -71,25 +71,6 @@ struct Stages {
   static constexpr int LPWX = 4;
 };
 
-// Calls f(integral_constant<U>) for U = 0, 1, ..., END-1 as straight-line
-// code, stopping after the first call that returns false.
-template <int U, int END, class F>
-__device__ __forceinline__ bool unrolled(F&& f) {
-  if constexpr (U < END) {
-    if (!f(std::integral_constant<int, U>{})) return false;
-    return unrolled<U + 1, END>(f);
-  }
-  return true;
-}
-
-// LDS buffer of stage u of the ring of three.
-template <int U>
-__device__ __forceinline__ v4f* ring_buf(v4f* b0, v4f* b1, v4f* b2) {
-  if constexpr (U % 3 == 0) return b0;
-  else if constexpr (U % 3 == 1) return b1;
-  else return b2;
-}
-
 // Copy stage st (row block st / PARTS, part st % PARTS) of both parity
 // tables into LDS buffer B.  Stages past the last row block re-read the
 // last one (into a buffer that is never read).
@@ -405,8 +386,6 @@ int legendre_ring_pad(int nk) {
     if (4 * k >= nk) return 4 * k;
   return -1;
 }
-
-int legendre_ncb(int groups) { return groups >= 2 ? 2 : 1; }
 
 hipError_t launch_legendre_analysis_batched(const BatchArgs& b, float2* y, float c_rest, hipStream_t st) {
   hipLaunchKernelGGL(analysis_batched, dim3(static_cast<unsigned>(8 * b.work_per)), dim3(128 * kBatchNcb), 0, st,
