@@ -221,7 +221,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
 // + lk.  Piece e of a row block is substep e / (KR/4), piece e % (KR/4).
 template <int NCB, int KS>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               float* __restrict__ W, v4f* b0, v4f* b1, v4f* b2) {
+                                               float* __restrict__ W, v4f* b0, v4f* b1, v4f* b2, float* spec) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
@@ -246,39 +246,42 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   // rows are zero, so they add nothing (the value is finite whenever the
   // field's own values are).  Lanes of fields past F read field 0; those
   // columns of the workspace are never read back.
+  // The four values of a row block arrive by 4-byte global->LDS copies in
+  // the wave's 1 KiB of the spectrum slot (value s of lane l at float
+  // 64 s + l), refilled at part 1 of every row block for the next one: no
+  // load into VGPRs is in flight beside the copies, so the compiler waits
+  // only for what a read needs.
   const float* yf = reinterpret_cast<const float*>(y);
   const int f = 8 * cb + (li >> 1);
   const bool fok = active && f < g.F;
   const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
-  auto bload = [&](int ib, int s) {
-    const int i = 16 * ib + 4 * s + lk;
-    const int l = i < np ? m + p + 2 * i : m;
-    return yf[(fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1)];
+  float* wspec = spec + wave * 256;
+  auto spec_copy = [&](int ib) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = 16 * ib + 4 * s + lk;
+      const int l = i < np ? m + p + 2 * i : m;
+      __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
+                                       wspec + 64 * s, 4, 0, 0);
+    }
   };
   floatx4 acc[KR];
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
   if (nb > 0) {
-    // Stage u issues the copies of stage u+2 and, when u opens a row block,
-    // then the B loads of the next row block.  The loads issued after the
-    // copies of stage s, which its wait has to leave in flight, are those
-    // of stage s+1 and the B loads issued at stages s-2 and s-1.  The
-    // prologue plays stages -2 and -1 the same way.
-    float bn[4], bc[4];
-    constexpr bool b_after_first = (PARTS == 2);  // stage -2 opens a row block
-    if (!b_after_first) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
-      asm volatile("" ::: "memory");
-    }
+    // Stage u issues the table copies of stage u+2 and, at part 1, the
+    // spectrum copies of the next row block (4 per wave).  Behind the table
+    // copies of stage s come those of stage s+1 and the spectrum copies of
+    // stages s-2 and s-1 if at part 1; at part 0 the spectrum copies of part
+    // 1 of the previous row block must be complete too, and only the table
+    // copies of the PARTS-2 stages in between follow them.  The prologue
+    // plays stages -2 and -1 the same way.
+    static_assert(PARTS == 2 || PARTS == 3, "spectrum refill at part 1");
     issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
-    if (b_after_first) {
-      asm volatile("" ::: "memory");
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bn[s] = bload(0, s);
-      asm volatile("" ::: "memory");
-    }
+    if constexpr (PARTS == 3) spec_copy(0);  // stage -2 is at part 1
     issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
+    if constexpr (PARTS == 2) spec_copy(0);  // stage -1 is at part 1
+    float bc[4];
     for (int st0 = 0; st0 < nst; st0 += S::NST) {
       unrolled<0, S::NST>([&](auto su_c) {
         constexpr int su = decltype(su_c)::value;
@@ -287,24 +290,18 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         if (st >= nst) return false;
         v4f* cur = ring_buf<su>(b0, b1, b2);
         v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
-        // B loads issued after this stage's copies: at stage s-2 (if part 0
-        // there) and at stage s-1 (if part 0 there)
         constexpr int pm2 = (part + 2 * PARTS - 2) % PARTS, pm1 = (part + PARTS - 1) % PARTS;
-        constexpr int nb_after = (pm2 == 0 ? 4 : 0) + (pm1 == 0 ? 4 : 0);
-        __builtin_amdgcn_s_waitcnt(vm_wait(LPW + nb_after));
+        constexpr int behind = LPW + (pm2 == 1 ? 4 : 0) + (pm1 == 1 ? 4 : 0);
+        constexpr int need = (part == 0 && (PARTS - 2) * LPW < behind) ? (PARTS - 2) * LPW : behind;
+        __builtin_amdgcn_s_waitcnt(vm_wait(need) & ~0x0F00);  // and every LDS read of this wave
         stage_barrier();
         const int ib = st / PARTS;
         if constexpr (part == 0) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) bc[q] = bn[q];
+          for (int q = 0; q < 4; ++q) bc[q] = wspec[64 * q + lane];
         }
         issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
-        if constexpr (part == 0) {
-          asm volatile("" ::: "memory");
-#pragma unroll
-          for (int q = 0; q < 4; ++q) bn[q] = bload(ib + 1, q);
-          asm volatile("" ::: "memory");
-        }
+        if constexpr (part == 1) spec_copy(ib + 1);
         if (active && ib < nbp) {
 #pragma unroll
           for (int tt = 0; tt < SC; ++tt) {
@@ -364,17 +361,18 @@ __global__ __launch_bounds__(128 * kBatchNcb) __attribute__((amdgpu_waves_per_eu
 __global__ __launch_bounds__(128 * kBatchNcb) __attribute__((amdgpu_waves_per_eu(3))) void synthesis_batched(
     const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y) {
   __shared__ v4f b0[kMaxStagePieces * 64], b1[kMaxStagePieces * 64], b2[kMaxStagePieces * 64];
+  __shared__ float spec[4 * 256];  // spectrum slot: 1 KiB per wave
   const int2 wk = take_work(work, per);
   if (wk.x < 0) return;
   const SegDev& sd = segs[wk.y >> 16];
   const int m = wk.x, c = wk.y & 0xffff;
   const float2* ys = y + sd.spec_off;
   switch (sd.g.kpad) {
-    case 64: synthesis_body<kBatchNcb, 16>(sd, m, c, ys, sd.work, b0, b1, b2); break;
-    case 128: synthesis_body<kBatchNcb, 32>(sd, m, c, ys, sd.work, b0, b1, b2); break;
-    case 192: synthesis_body<kBatchNcb, 48>(sd, m, c, ys, sd.work, b0, b1, b2); break;
-    case 256: synthesis_body<kBatchNcb, 64>(sd, m, c, ys, sd.work, b0, b1, b2); break;
-    default: synthesis_body<kBatchNcb, 96>(sd, m, c, ys, sd.work, b0, b1, b2); break;
+    case 64: synthesis_body<kBatchNcb, 16>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
+    case 128: synthesis_body<kBatchNcb, 32>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
+    case 192: synthesis_body<kBatchNcb, 48>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
+    case 256: synthesis_body<kBatchNcb, 64>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
+    default: synthesis_body<kBatchNcb, 96>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
   }
 }
 

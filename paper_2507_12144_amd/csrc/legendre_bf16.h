@@ -71,27 +71,37 @@ __device__ __forceinline__ void products(const bf16x8* a, const bf16x8* b, float
 }
 
 // Steps per stage: the largest divisor of the steps of a row block whose
-// NP planes fit in 8 pieces.
-constexpr int steps_per_stage(int steps, int np) {
+// NP planes fit in 8 pieces and that leaves at least min_parts stages per
+// row block.
+constexpr int steps_per_stage(int steps, int np, int min_parts) {
   for (int ss = steps; ss > 1; --ss)
-    if (steps % ss == 0 && ss * np <= 8) return ss;
+    if (steps % ss == 0 && ss * np <= 8 && steps / ss >= min_parts) return ss;
   return 1;
 }
 
 // Stage geometry: steps of K = 32 per row block, SS steps (SC = SS * NP
 // pieces per parity) per stage, PARTS stages per row block; NST stages
 // unrolled into straight-line code (lmax <= 2 kpad; larger lmax goes round
-// an outer loop), a multiple of the period of buffer (stage % 3) and part.
-template <int STEPS, int NP, int MAXBLK>
+// an outer loop), a multiple of the period of buffer (stage % NBUF) and
+// part.
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+template <int STEPS, int NP, int MAXBLK, int NBUF, int MIN_PARTS = 1>
 struct Geo {
-  static constexpr int SS = steps_per_stage(STEPS, NP);
+  static constexpr int SS = steps_per_stage(STEPS, NP, MIN_PARTS);
   static constexpr int SC = SS * NP;
   static constexpr int PARTS = STEPS / SS;
   static constexpr int LPW = (2 * SC + 3) / 4;  // copies per wave and stage (4 waves)
-  static constexpr int PERIOD = (PARTS % 3 == 0) ? PARTS : 3 * PARTS;
+  static constexpr int PERIOD = PARTS / gcd_c(PARTS, NBUF) * NBUF;
   static constexpr int NST = ((PARTS * MAXBLK + PERIOD - 1) / PERIOD) * PERIOD;
   static_assert(2 * SC <= 16, "stage buffer");
 };
+
+// Buffers of the LDS ring: NBUF stages of 16 pieces (16 KiB); stage g
+// lives in buffer g % NBUF and is copied NBUF - 1 stages ahead.
+template <int G, int NBUF>
+__device__ __forceinline__ v4f* rbuf(v4f* ring) {
+  return ring + (G % NBUF) * 16 * 64;
+}
 
 // Copy stage st (row block st / PARTS, part st % PARTS) of both parities:
 // piece e < 2 SC of the stage is parity e / SC, piece e % SC; pieces are
@@ -114,16 +124,50 @@ __device__ __forceinline__ void issue_stage(v4f* B, const uint16_t* __restrict__
 
 __device__ __forceinline__ bf16x8 as_bf16x8(v4f v) { return __builtin_bit_cast(bf16x8, v); }
 
+// Wait for vector memory (at most n copies of this wave in flight) and for
+// every LDS read of this wave, so that after the barrier that follows no
+// wave still reads a buffer the next copies overwrite.
+constexpr int vm_lds_wait(int n) { return vm_wait(n) & ~0x0F00; }
+
+// Copies per wave in flight behind global analysis stage gs: those of
+// stages gs+1 .. gs+D-1 (four for a stage of S / A, LPW for a table stage).
+template <int XS, int LPW, int D>
+constexpr int x_behind(int gs) {
+  int n = 0;
+  for (int i = 1; i < D; ++i) n += (gs + i < XS) ? 4 : LPW;
+  return n;
+}
+
+// Synthesis: copies in flight that stage s may leave outstanding.  Stage j
+// issues the table copies of stage j+D and, at part 1, the NB spectrum
+// copies of the next row block.  Behind the table copies of stage s come
+// those of stages s+1 .. s+D-1 and the spectrum copies of every stage
+// s-D .. s-1 at part 1; a stage at part 0 also needs the spectrum copies
+// issued at part 1 of the previous row block, which only the table copies
+// of the PARTS-2 stages in between follow.
+template <int PARTS, int LPW, int D, int NB>
+constexpr int s_behind(int s) {
+  int n = (D - 1) * LPW;
+  for (int j = s - D; j < s; ++j)
+    if (((j % PARTS) + PARTS) % PARTS == 1) n += NB;
+  if (s % PARTS == 0 && (PARTS - 2) * LPW < n) n = (PARTS - 2) * LPW;
+  return n;
+}
+
+
 // Analysis.  Contraction index k of a wave's K slice = lk * KS + 8t + e for
-// lane group lk, step t (K = 32: 8 values a lane) and element e.
-template <int KS, int NP>
+// lane group lk, step t (K = 32: 8 values a lane) and element e.  Global
+// stage g < XS brings rings 16g .. 16g+15 of every lane group's K slice of
+// S or A (each wave its own four pieces); stage XS + s is table stage s.
+template <int KS, int NP, int NBUF>
 __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, float2* __restrict__ y, float c_rest,
-                                              v4f* b0, v4f* b1, v4f* b2) {
+                                              v4f* ring) {
   constexpr int T8 = KS / 8;  // steps per 16-row block
-  using G = Geo<T8, NP, KS / 4>;
+  using G = Geo<T8, NP, KS / 4, NBUF>;
   constexpr int SC = G::SC, SS = G::SS, LPW = G::LPW, PARTS = G::PARTS;
   constexpr int KPAD = 4 * KS;
-  constexpr int XS = KS / 16;  // stages of S / A (16 rings per lane group)
+  constexpr int XS = KS / 16;
+  constexpr int D = NBUF - 1;  // stages in flight
   const SegGeom& g = sd.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave >> 1, j = wave & 1;
@@ -144,29 +188,28 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   const bool fok = active && f < g.F;
   if (nb > 0) {
     bf16x8 xs[T8][NP];
-    // stage u < XS: rings lk * KS + 16u .. +15 of every lane group of every
-    // wave (piece 4 wave + lk); table stage s follows as stage XS + s
-    auto issue_x = [&](v4f* B, int u) {
+    auto issue = [&](auto g_c, int tab_st) {
+      constexpr int gs = decltype(g_c)::value;
+      v4f* B = rbuf<gs, NBUF>(ring);
+      if constexpr (gs < XS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        __builtin_amdgcn_global_load_lds(Wg + (q * KS + 16 * u) * 16 + lane * 4, B + (4 * wave + q) * 64, 16, 0, 0);
+        for (int q = 0; q < 4; ++q)
+          __builtin_amdgcn_global_load_lds(Wg + (q * KS + 16 * gs) * 16 + lane * 4, B + (4 * wave + q) * 64, 16, 0,
+                                           0);
+      } else {
+        issue_stage<SC, LPW, PARTS>(B, tab, 2 * nb32, nb, T8 * NP, tab_st, wave, lane);
+      }
     };
-    issue_x(b0, 0);
-    if constexpr (XS > 1)
-      issue_x(b1, 1);
-    else
-      issue_stage<SC, LPW, PARTS>(b1, tab, 2 * nb32, nb, T8 * NP, 0, wave, lane);
+    unrolled<0, D>([&](auto g_c) {
+      issue(g_c, decltype(g_c)::value - XS);
+      return true;
+    });
     unrolled<0, XS>([&](auto u_c) {
       constexpr int u = decltype(u_c)::value;
-      v4f* cur = ring_buf<u>(b0, b1, b2);
-      v4f* nxt = ring_buf<u + 2>(b0, b1, b2);
-      __builtin_amdgcn_s_waitcnt(vm_wait(u + 1 < XS ? 4 : LPW));
+      __builtin_amdgcn_s_waitcnt(vm_lds_wait(x_behind<XS, LPW, D>(u)));
       stage_barrier();
-      if constexpr (u + 2 < XS)
-        issue_x(nxt, u + 2);
-      else
-        issue_stage<SC, LPW, PARTS>(nxt, tab, 2 * nb32, nb, T8 * NP, u + 2 - XS, wave, lane);
-      const float* xb = reinterpret_cast<const float*>(cur) + (4 * wave + lk) * 256 + li;
+      issue(std::integral_constant<int, u + D>{}, u + D - XS);
+      const float* xb = reinterpret_cast<const float*>(rbuf<u, NBUF>(ring)) + (4 * wave + lk) * 256 + li;
       float v[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = xb[16 * r];
@@ -181,11 +224,10 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
         constexpr int part = su % PARTS;
         const int st = st0 + su;
         if (st >= nst) return false;
-        v4f* cur = ring_buf<su + XS>(b0, b1, b2);
-        v4f* nxt = ring_buf<su + XS + 2>(b0, b1, b2);
-        __builtin_amdgcn_s_waitcnt(vm_wait(LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait((D - 1) * LPW));
         stage_barrier();
-        issue_stage<SC, LPW, PARTS>(nxt, tab, 2 * nb32, nb, T8 * NP, st + 2, wave, lane);
+        issue(std::integral_constant<int, XS + su + D>{}, st + D);
+        const v4f* cur = rbuf<XS + su, NBUF>(ring);
         const int ib = st / PARTS;
         if (active && ib < nbp) {
 #pragma unroll
@@ -230,15 +272,21 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
 }
 
 // Synthesis.  Contraction rows i = 32 ib + 8 lk + e of the wave's parity;
-// output ring k = (MFMA row) * KR + rb for step rb of a 32-row block.
-template <int KS, int NP>
+// output ring k = (MFMA row) * KR + rb for step rb of a 32-row block.  The
+// spectrum values of a row block (the B operand: 8 per lane) arrive by
+// 4-byte global->LDS copies into one slot of 2 KiB per wave (value e of
+// lane l at float 64 e + l): all loads in flight are LDS copies, so every
+// wait is one of the counted waits below.
+template <int KS, int NP, int NBUF>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               v4f* b0, v4f* b1, v4f* b2) {
+                                               v4f* ring, float* spec) {
   constexpr int KPAD = 4 * KS;
   constexpr int KR = KPAD / 16;  // steps (16-ring output blocks) per 32-row block
-  using G = Geo<KR, NP, KS / 8>;
+  using G = Geo<KR, NP, KS / 8, NBUF, 2>;
   constexpr int SC = G::SC, SS = G::SS, LPW = G::LPW, PARTS = G::PARTS;
-  constexpr int NB = 8;  // B loads per lane and row block
+  static_assert(PARTS >= 2, "the spectrum slot is refilled at part 1");
+  constexpr int NB = 8;  // spectrum copies per wave and row block
+  constexpr int D = NBUF - 1;
   const SegGeom& g = sd.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = wave >> 1, j = wave & 1;
@@ -259,41 +307,30 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   const int f = 8 * cb + (li >> 1);
   const bool fok = active && f < g.F;
   const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
-  float bn[NB];
-  auto bload = [&](int ib) {
+  float* wspec = spec + wave * 64 * NB;
+  auto spec_copy = [&](int ib) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
       const int i = 32 * ib + 8 * lk + e;
       const int l = i < np ? m + p + 2 * i : m;
-      bn[e] = yf[(fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1)];
+      __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
+                                       wspec + 64 * e, 4, 0, 0);
     }
   };
   floatx4 acc[KR];
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
   if (nb32 > 0) {
-    // Stage u issues the copies of stage u+2 and then, when it opens a row
-    // block, the B loads of the next one; the prologue plays stages -2 and
-    // -1 the same way (B loads of row block 0 first when neither opens a
-    // block).  The loads issued after the copies of stage s are those of
-    // stage s+1 and the B loads of stages s-2 and s-1 that open blocks.
-    constexpr int pm2 = ((-2 % PARTS) + PARTS) % PARTS, pm1 = PARTS - 1;
-    if constexpr (pm2 != 0 && pm1 != 0) {
-      bload(0);
-      asm volatile("" ::: "memory");
-    }
-    issue_stage<SC, LPW, PARTS>(b0, tab, nb32, nb32, KR * NP, 0, wave, lane);
-    if constexpr (pm2 == 0) {
-      asm volatile("" ::: "memory");
-      bload(0);
-      asm volatile("" ::: "memory");
-    }
-    issue_stage<SC, LPW, PARTS>(b1, tab, nb32, nb32, KR * NP, 1, wave, lane);
-    if constexpr (pm1 == 0) {
-      asm volatile("" ::: "memory");
-      bload(0);
-      asm volatile("" ::: "memory");
-    }
+    // The prologue plays stages -D .. -1 as the loop does (table copies of
+    // stage v+D, then the spectrum of row block 0 where v is at part 1);
+    // when none of them is at part 1, row block 0's spectrum goes first.
+    if constexpr (PARTS > D + 1) spec_copy(0);
+    unrolled<0, D>([&](auto i_c) {
+      constexpr int i = decltype(i_c)::value;
+      issue_stage<SC, LPW, PARTS>(rbuf<i, NBUF>(ring), tab, nb32, nb32, KR * NP, i, wave, lane);
+      if constexpr ((((i - D) % PARTS) + PARTS) % PARTS == 1) spec_copy(0);
+      return true;
+    });
     bf16x8 bv[NP];
     for (int st0 = 0; st0 < nst; st0 += G::NST) {
       unrolled<0, G::NST>([&](auto su_c) {
@@ -301,19 +338,18 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         constexpr int part = su % PARTS;
         const int st = st0 + su;
         if (st >= nst) return false;
-        v4f* cur = ring_buf<su>(b0, b1, b2);
-        v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
-        constexpr int q2 = (part + 2 * PARTS - 2) % PARTS, q1 = (part + PARTS - 1) % PARTS;
-        __builtin_amdgcn_s_waitcnt(vm_wait(LPW + NB * ((q2 == 0 ? 1 : 0) + (q1 == 0 ? 1 : 0))));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(s_behind<PARTS, LPW, D, NB>(su)));
         stage_barrier();
         const int ib = st / PARTS;
-        if constexpr (part == 0) split8<NP>(bn, bv);
-        issue_stage<SC, LPW, PARTS>(nxt, tab, nb32, nb32, KR * NP, st + 2, wave, lane);
         if constexpr (part == 0) {
-          asm volatile("" ::: "memory");
-          bload(ib + 1);
-          asm volatile("" ::: "memory");
+          float bn[NB];
+#pragma unroll
+          for (int e = 0; e < NB; ++e) bn[e] = wspec[64 * e + lane];
+          split8<NP>(bn, bv);
         }
+        issue_stage<SC, LPW, PARTS>(rbuf<su + D, NBUF>(ring), tab, nb32, nb32, KR * NP, st + D, wave, lane);
+        if constexpr (part == 1) spec_copy(ib + 1);
+        const v4f* cur = rbuf<su, NBUF>(ring);
         if (active && ib < nbp) {
 #pragma unroll
           for (int s = 0; s < SS; ++s) {
@@ -336,45 +372,55 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
     for (int r = 0; r < 4; ++r) Wp[((4 * lk + r) * KR + rb) * 16 + li] = acc[rb][r];
 }
 
-// Waves per SIMD the kernels are compiled for: 3 (168 VGPRs) holds the
-// one-plane operands; the split forms keep NP planes of the data in VGPRs
-// (up to 144 of them at 384 rings) and get 256.
-constexpr int waves_per_eu(int np) { return np == 1 ? 3 : 2; }
+// LDS ring depth and waves per SIMD: five 16 KiB buffers (four stages in
+// flight) take half of the CU's 160 KiB, so two workgroups share a CU and
+// each wave may use 256 VGPRs (the split forms keep NP planes of the data in
+// VGPRs, up to 144 of them at 384 rings).
+constexpr int kRingBuffers = 5;
+// Synthesis: four buffers plus the 8 KiB spectrum slot.
+constexpr int kSynBuffers = 4;
 
 // Batched kernels of one plane count (items {m, (segment << 16) | chunk}).
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu(NP)))) void analysis_batched(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void analysis_batched(
     const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest) {
-  __shared__ v4f b0[16 * 64], b1[16 * 64], b2[16 * 64];
+  __shared__ v4f ring[kRingBuffers * 16 * 64];
   const int2 wk = take_work(work, per);
   if (wk.x < 0) return;
   const SegDev& sd = segs[wk.y >> 16];
   const int m = wk.x, c = wk.y & 0xffff;
   float2* ys = y + sd.spec_off;
+  constexpr int R = kRingBuffers;
   switch (sd.g.kpad) {
-    case 64: analysis_body<16, NP>(sd, m, c, ys, c_rest, b0, b1, b2); break;
-    case 128: analysis_body<32, NP>(sd, m, c, ys, c_rest, b0, b1, b2); break;
-    case 192: analysis_body<48, NP>(sd, m, c, ys, c_rest, b0, b1, b2); break;
-    case 256: analysis_body<64, NP>(sd, m, c, ys, c_rest, b0, b1, b2); break;
-    default: analysis_body<96, NP>(sd, m, c, ys, c_rest, b0, b1, b2); break;
+    case 64: analysis_body<16, NP, R>(sd, m, c, ys, c_rest, ring); break;
+    case 128: analysis_body<32, NP, R>(sd, m, c, ys, c_rest, ring); break;
+    case 192: analysis_body<48, NP, R>(sd, m, c, ys, c_rest, ring); break;
+    case 256: analysis_body<64, NP, R>(sd, m, c, ys, c_rest, ring); break;
+    default: analysis_body<96, NP, R>(sd, m, c, ys, c_rest, ring); break;
   }
 }
 
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu(NP)))) void synthesis_batched(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void synthesis_batched(
     const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y) {
-  __shared__ v4f b0[16 * 64], b1[16 * 64], b2[16 * 64];
+  // one LDS variable for the ring and the spectrum slot: the compiler then
+  // leaves the copies to the counted waits instead of waiting for the
+  // newest copy into a variable before every read of it
+  __shared__ v4f lds[kSynBuffers * 16 * 64 + 4 * 64 * 8 / 4];
+  v4f* ring = lds;
+  float* spec = reinterpret_cast<float*>(lds + kSynBuffers * 16 * 64);
   const int2 wk = take_work(work, per);
   if (wk.x < 0) return;
   const SegDev& sd = segs[wk.y >> 16];
   const int m = wk.x, c = wk.y & 0xffff;
   const float2* ys = y + sd.spec_off;
+  constexpr int R = kSynBuffers;
   switch (sd.g.kpad) {
-    case 64: synthesis_body<16, NP>(sd, m, c, ys, b0, b1, b2); break;
-    case 128: synthesis_body<32, NP>(sd, m, c, ys, b0, b1, b2); break;
-    case 192: synthesis_body<48, NP>(sd, m, c, ys, b0, b1, b2); break;
-    case 256: synthesis_body<64, NP>(sd, m, c, ys, b0, b1, b2); break;
-    default: synthesis_body<96, NP>(sd, m, c, ys, b0, b1, b2); break;
+    case 64: synthesis_body<16, NP, R>(sd, m, c, ys, ring, spec); break;
+    case 128: synthesis_body<32, NP, R>(sd, m, c, ys, ring, spec); break;
+    case 192: synthesis_body<48, NP, R>(sd, m, c, ys, ring, spec); break;
+    case 256: synthesis_body<64, NP, R>(sd, m, c, ys, ring, spec); break;
+    default: synthesis_body<96, NP, R>(sd, m, c, ys, ring, spec); break;
   }
 }
 
