@@ -17,6 +17,7 @@
 //    block order is remapped so that the workgroups completing one 128-byte
 //    line run together on the same XCD (which merges them in its L2).
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernel_common.h"
@@ -282,6 +283,12 @@ struct FastFFT {
   }
 };
 
+// Ring width fixed at compile time (FastFFT), or 0 (GenericFFT).
+template <class T, class = void>
+struct fixed_width : std::integral_constant<int, 0> {};
+template <class T>
+struct fixed_width<T, std::void_t<decltype(T::N)>> : std::integral_constant<int, T::N> {};
+
 // Runtime radices (4, 2, 3, 5), ping-pong buffers: any N = 2^a 3^b 5^c.
 template <int R>
 __device__ __forceinline__ void pingpong_bfly(const float2* __restrict__ src, float2* __restrict__ dst, int tt,
@@ -372,7 +379,39 @@ __device__ __forceinline__ void dft_forward_body(const DftArgs& a, const Item& i
   FFT::prepare(lds, a, tw);
   // load 4 fields x 2 rings, packed as complex (north, mirrored ring)
   const int nq = N / 4;
-  if ((N & 3) == 0) {
+  constexpr int NF = fixed_width<FFT>::value;
+  if constexpr (NF > 0 && NF % 4 == 0) {
+    // every load of the thread is issued before the first LDS store, so the
+    // workgroup waits for one memory round trip, not one per iteration
+    constexpr int NQ = NF / 4, TOT = FGW * NQ, PER = (TOT + NT - 1) / NT;
+    float4 vn[PER], vs[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + b * NT;
+      const int fl = idx / NQ;
+      const int j = 4 * (idx - fl * NQ);
+      const int fi = f0 + fl;
+      vn[b] = make_float4(0.f, 0.f, 0.f, 0.f);
+      vs[b] = vn[b];
+      if (idx < TOT && fi < a.F) {
+        vn[b] = *reinterpret_cast<const float4*>(x + (static_cast<size_t>(fi) * a.nlat + kk) * NF + j);
+        if (!eq) vs[b] = *reinterpret_cast<const float4*>(x + (static_cast<size_t>(fi) * a.nlat + ks) * NF + j);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int idx = threadIdx.x + b * NT;
+      if (idx < TOT) {
+        const int fl = idx / NQ;
+        const int j = 4 * (idx - fl * NQ);
+        float2* d = lds + fl * NF + j;
+        d[0] = make_float2(vn[b].x, vs[b].x);
+        d[1] = make_float2(vn[b].y, vs[b].y);
+        d[2] = make_float2(vn[b].z, vs[b].z);
+        d[3] = make_float2(vn[b].w, vs[b].w);
+      }
+    }
+  } else if ((N & 3) == 0) {
     for (int idx = threadIdx.x; idx < FGW * nq; idx += NT) {
       const int fl = idx / nq;
       const int j = 4 * (idx - fl * nq);
@@ -449,19 +488,10 @@ __device__ __forceinline__ void dft_inverse_body(const DftArgs& a, const Item& i
   const bool eq = (ks == kk);
   const int f0 = 8 * it.g + 4 * it.hh;
   FFT::prepare(lds, a, tw);
-  for (int idx = threadIdx.x; idx < FGW * N; idx += NT) lds[idx] = make_float2(0.f, 0.f);
-  __syncthreads();
   const float h = 0.5f * a.c_rest;
-  for (int m = threadIdx.x; m < a.mmax; m += NT) {
-    const float4* pe = reinterpret_cast<const float4*>(W + wrow(a, m, 0, it.g, kk) + 8 * it.hh);
-    const float4 e0 = pe[0], e1 = pe[1];
-    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0;
-    // order m has odd-parity degrees only when m + 1 < lmax
-    if (m + 1 < a.lmax) {
-      const float4* po = reinterpret_cast<const float4*>(W + wrow(a, m, 1, it.g, kk) + 8 * it.hh);
-      o0 = po[0];
-      o1 = po[1];
-    }
+  // E = W[m][0], O = W[m][1] of this item's 4 fields -> spectra of the two
+  // rings, placed at bins m and N - m of the packed sequence
+  auto place = [&](int m, float4 e0, float4 e1, float4 o0, float4 o1) {
     const float Ev[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
     const float Ov[8] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z, o1.w};
 #pragma unroll
@@ -477,6 +507,46 @@ __device__ __forceinline__ void dft_inverse_body(const DftArgs& a, const Item& i
         lds[fl * N + m] = make_float2(hn.x - hs.y, hn.y + hs.x);
         lds[fl * N + N - m] = make_float2(hn.x + hs.y, -hn.y + hs.x);
       }
+    }
+  };
+  // order m has odd-parity degrees only when m + 1 < lmax
+  auto load = [&](int m, float4& e0, float4& e1, float4& o0, float4& o1) {
+    const float4* pe = reinterpret_cast<const float4*>(W + wrow(a, m, 0, it.g, kk) + 8 * it.hh);
+    e0 = pe[0];
+    e1 = pe[1];
+    o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    o1 = o0;
+    if (m + 1 < a.lmax) {
+      const float4* po = reinterpret_cast<const float4*>(W + wrow(a, m, 1, it.g, kk) + 8 * it.hh);
+      o0 = po[0];
+      o1 = po[1];
+    }
+  };
+  constexpr int NF = fixed_width<FFT>::value;
+  if constexpr (NF > 0) {
+    // all loads of the thread first (m < mmax <= NF / 2), then the zero
+    // fill of the buffer, then the stores of the loaded bins
+    constexpr int PER = (NF / 2 + NT - 1) / NT;
+    float4 e0[PER], e1[PER], o0[PER], o1[PER];
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int m = threadIdx.x + b * NT;
+      if (m < a.mmax) load(m, e0[b], e1[b], o0[b], o1[b]);
+    }
+    for (int idx = threadIdx.x; idx < FGW * N; idx += NT) lds[idx] = make_float2(0.f, 0.f);
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < PER; ++b) {
+      const int m = threadIdx.x + b * NT;
+      if (m < a.mmax) place(m, e0[b], e1[b], o0[b], o1[b]);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < FGW * N; idx += NT) lds[idx] = make_float2(0.f, 0.f);
+    __syncthreads();
+    for (int m = threadIdx.x; m < a.mmax; m += NT) {
+      float4 e0, e1, o0, o1;
+      load(m, e0, e1, o0, o1);
+      place(m, e0, e1, o0, o1);
     }
   }
   __syncthreads();
