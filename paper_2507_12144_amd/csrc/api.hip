@@ -146,7 +146,7 @@ struct sht_plan_s {
   int2* bwork = nullptr;
   sht::BatchArgs batch{};
   // schedule (sht_plan_tune): orders per chunk, XCD dealing policy
-  int tune_chunk = 16, tune_policy = 0;
+  int tune_chunk = 8, tune_policy = 0;
   int graphs = 0;  // live sht_graph_t objects of this plan
 };
 
@@ -684,7 +684,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   struct Cand {
     int chunk, policy;
   };
-  const std::vector<Cand> cands = {{16, 0}, {4, 0}, {8, 0}, {32, 0}, {16, 1}, {8, 1}};
+  const std::vector<Cand> cands = {{8, 0}, {4, 0}, {16, 0}, {32, 0}, {8, 1}, {16, 1}};
   auto apply = [&](const Cand& c) {
     plan->tune_chunk = c.chunk;
     plan->tune_policy = c.policy;
