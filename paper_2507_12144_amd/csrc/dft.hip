@@ -26,7 +26,7 @@ namespace sht {
 namespace {
 
 constexpr int FGW = 4;     // fields per workgroup
-constexpr int NT = 256;    // threads per workgroup
+constexpr int NT = 512;    // threads per workgroup
 
 struct DftArgs {
   int nlat, nlon, lmax, mmax, nk, F, kpad, G;
