@@ -15,14 +15,6 @@ __device__ __forceinline__ int2 take_work(const int2* __restrict__ work, int per
   return work[slot];
 }
 
-// Depth of an operand prefetch ring: the largest divisor of the steps per
-// row block that does not exceed `cap`.
-constexpr int ring_depth(int steps, int cap = 8) {
-  for (int d = cap; d > 1; --d)
-    if (steps % d == 0) return d;
-  return 1;
-}
-
 }  // namespace sht
 
 namespace sht {

@@ -17,12 +17,14 @@
 // Structure as in the float32 kernels: one workgroup of four waves per
 // (segment, m, chunk of two field groups), wave (p, j) owns parity p and one
 // 16-column field group; the table pieces (1 KiB: one plane of one K = 32
-// step of a 16-row block, 16 bytes a lane) flow through a ring of three LDS
+// step of a 16-row block, 16 bytes a lane) flow through a ring of 16 KiB LDS
 // buffers filled by asynchronous global->LDS copies, each stage carrying SS
-// steps x NP planes for both parities.  Analysis: the wave's K slice of S or
-// A arrives through the ring first and is split into planes in VGPRs.
-// Synthesis: 32-row blocks (K = 32), the spectrum values of the next block
-// are loaded one block ahead and split when their block starts.
+// steps x NP planes for both parities.  Analysis: five buffers (four stages
+// in flight); the wave's K slice of S or A arrives through the ring first
+// and is split into planes in VGPRs.  Synthesis: four buffers and a
+// spectrum slot; 32-row blocks (K = 32), the spectrum values of the next
+// block arrive by 4-byte copies during the current one and are split when
+// their block starts.
 #pragma once
 
 #include "bf16.h"
