@@ -24,7 +24,12 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    """The HIP sources, the slowest to compile (the per-plane-count bf16
+    kernels, then the float32 contraction) first, so that the parallel build
+    ends soonest."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    order = lambda f: (0 if "_np" in f else 1 if f.startswith("legendre") else 2, f)
+    return [os.path.join(CSRC, f) for f in sorted(names, key=order)]
 
 
 def _compile(src):
