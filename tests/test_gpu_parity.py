@@ -23,8 +23,11 @@ TOL = 1e-5
 
 
 def _say(*a):
+    """Progress line: into pytest's captured output (shown with a failure)
+    and, live, on the process's real stderr, so that a long test shows its
+    steps while it runs."""
     print(*a, flush=True)
-    sys.stdout.flush()
+    print(*a, file=sys.__stderr__, flush=True)
 
 
 @pytest.fixture(scope="module")
