@@ -29,11 +29,11 @@ from .grids import (equiangular_nodes, gauss_legendre, clenshaw_curtis_weights,
                     trapezoid_weights, grid)
 from .legendre import legendre_order, legendre_table
 from .transforms import sht, isht, sht_T, isht_T, sht_bruteforce, isht_bruteforce
-from .mix import channel_mix, channel_mix_T
+from .mix import channel_mix, channel_mix_T, channel_mix_dW
 
 __all__ = [
     "equiangular_nodes", "gauss_legendre", "clenshaw_curtis_weights",
     "trapezoid_weights", "grid", "legendre_order", "legendre_table",
     "sht", "isht", "sht_T", "isht_T", "sht_bruteforce", "isht_bruteforce",
-    "channel_mix", "channel_mix_T",
+    "channel_mix", "channel_mix_T", "channel_mix_dW",
 ]

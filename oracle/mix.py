@@ -30,3 +30,26 @@ def channel_mix_T(g, W):
     """Adjoint of ``channel_mix`` with respect to x."""
     W = np.asarray(W, dtype=np.complex128)
     return channel_mix(g, np.conj(np.transpose(W, (0, 2, 1))))
+
+
+def channel_mix_dW(g, x):
+    """Gradient of a real loss with respect to the weights of ``channel_mix``,
+    in PyTorch's complex convention (dL/dRe W + i dL/dIm W), from the gradient
+    g = dL/dRe y + i dL/dIm y of y = channel_mix(x, W):
+
+        dW[l, c', c] = sum_b sum_{m <= l} g[b, c', l, m] conj(x[b, c, l, m])
+
+    i.e. per degree the product G_l X_l^H of the (channels x (b, m)) matrices,
+    over the stored orders m <= min(l, mmax - 1) to which the filter of
+    eq. s2_spectral_conv applies (entries l < m of a spectrum are zero).
+    g, x: complex [B, C, lmax, mmax] -> dW: complex [lmax, C, C]."""
+    g = np.asarray(g, dtype=np.complex128)
+    x = np.asarray(x, dtype=np.complex128)
+    B, C, lmax, mmax = x.shape
+    dW = np.zeros((lmax, C, C), dtype=np.complex128)
+    for l in range(lmax):
+        mc = min(l + 1, mmax)
+        gl = np.transpose(g[:, :, l, :mc], (1, 0, 2)).reshape(C, B * mc)
+        xl = np.transpose(x[:, :, l, :mc], (1, 0, 2)).reshape(C, B * mc)
+        dW[l] = gl @ np.conj(xl).T
+    return dW

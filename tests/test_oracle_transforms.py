@@ -193,6 +193,91 @@ def test_chain_gradient_against_finite_differences():
         assert abs(fd - np.sum(grad * v)) <= 1e-9 * np.linalg.norm(grad) * np.linalg.norm(v)
 
 
+def test_channel_mix_weight_gradient_pins():
+    """dW = channel_mix_dW(g, x) pinned without its own matrix products:
+    (a) the exact directional derivative of the linear loss
+    L(W) = Re <G, mix_W(x)> along V equals Re <dW, V> (the forward mix is a
+    separate code path); (b) brute-force loops on a tiny case; (c) entries
+    with m > l (where the filter does not act) contribute nothing."""
+    B, C, L, M = 2, 4, 6, 5
+    x = synth.coefficients(11, B, C, L, M)            # zero for l < m
+    G = synth.coefficients(12, B, C, L, M)
+    dW = oracle.channel_mix_dW(G, x)
+    rng = np.random.default_rng(13)
+    for _ in range(4):
+        V = rng.standard_normal((L, C, C)) + 1j * rng.standard_normal((L, C, C))
+        assert abs(_rdot(G, oracle.channel_mix(x, V)) - _rdot(dW, V)) < 1e-12
+    ref = np.zeros((L, C, C), complex)
+    for l in range(L):
+        for co in range(C):
+            for ci in range(C):
+                for b in range(B):
+                    for m in range(min(l + 1, M)):
+                        ref[l, co, ci] += G[b, co, l, m] * np.conj(x[b, ci, l, m])
+    np.testing.assert_allclose(dW, ref, atol=1e-13)
+    x2, G2 = x.copy(), G.copy()
+    for l in range(L):
+        x2[:, :, l, l + 1:] = 7.0 + 3.0j
+        G2[:, :, l, l + 1:] = -5.0 + 1.0j
+    np.testing.assert_allclose(oracle.channel_mix_dW(G2, x2), dW, atol=0)
+
+
+def test_weight_gradient_pins_catch_planted_mistakes():
+    """Plausible mistakes in the weight gradient, planted in copies on the
+    CPU: each must break the directional-derivative identity or the mask."""
+    B, C, L, M = 2, 3, 5, 4
+    x = synth.coefficients(31, B, C, L, M)
+    G = synth.coefficients(32, B, C, L, M)
+    rng = np.random.default_rng(33)
+    V = rng.standard_normal((L, C, C)) + 1j * rng.standard_normal((L, C, C))
+    x2, G2 = x.copy(), G.copy()
+    for l in range(L):
+        x2[:, :, l, l + 1:] = 2.0 - 1.0j
+        G2[:, :, l, l + 1:] = 1.0 + 4.0j
+
+    def all_m(g, xx):  # no m <= l restriction
+        return np.einsum("bclm,bdlm->lcd", g, np.conj(xx))
+
+    def m_below_l(g, xx):  # m < l instead of m <= l
+        out = np.zeros((L, C, C), complex)
+        for l in range(L):
+            out[l] = np.einsum("bcm,bdm->cd", g[:, :, l, :min(l, M)], np.conj(xx[:, :, l, :min(l, M)]))
+        return out
+
+    wrong = {
+        "conj on g": lambda g, xx: np.conj(oracle.channel_mix_dW(g, xx)),
+        "transposed": lambda g, xx: np.transpose(oracle.channel_mix_dW(g, xx), (0, 2, 1)),
+        "all m": all_m,
+        "m < l": m_below_l,
+    }
+    for name, f in wrong.items():
+        identity = abs(_rdot(G, oracle.channel_mix(x, V)) - _rdot(f(G, x), V)) < 1e-12
+        masked = np.allclose(f(G2, x2), f(G, x))
+        assert not (identity and masked), name
+
+
+def test_weight_gradient_of_the_chain_against_finite_differences():
+    # L(W) = <r, ISHT(mix_W(SHT(x)))>: dL/dW = channel_mix_dW(ISHT^T(r), SHT(x))
+    # in PyTorch's convention (dL/dRe W + i dL/dIm W), against central
+    # differences along random complex directions (h = 1e-3; L is linear in W)
+    nlat, nlon, Lm, B, C = 12, 24, 12, 2, 3
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((B, C, nlat, nlon))
+    r = rng.standard_normal((B, C, nlat, nlon))
+    W = synth.mix_weights(4, Lm, C)
+    xh = oracle.sht(x, Lm, Lm, 1)
+
+    def loss(Wv):
+        return float(np.sum(r * oracle.isht(oracle.channel_mix(xh, Wv), nlat, nlon, 1)))
+
+    dW = oracle.channel_mix_dW(oracle.isht_T(r, Lm, Lm, 1), xh)
+    h = 1e-3
+    for _ in range(6):
+        V = rng.standard_normal(W.shape) + 1j * rng.standard_normal(W.shape)
+        fd = (loss(W + h * V) - loss(W - h * V)) / (2 * h)
+        assert abs(fd - _rdot(dW, V)) <= 1e-9 * np.linalg.norm(dW) * np.linalg.norm(V)
+
+
 def test_input_validation():
     u = np.zeros((8, 16))
     with pytest.raises(ValueError):
