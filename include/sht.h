@@ -152,6 +152,17 @@ sht_status isht_backward(sht_plan_t plan, const float* gx, void* gy, void* hip_s
 sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void* out,
                            int adjoint, void* hip_stream);
 
+/* Weight gradient of sht_channel_mix (plan with one segment): for a real
+ * loss L of y = sht_channel_mix(W, x), given g = dL/dRe y + i dL/dIm y,
+ *   dW[l,c',c] = sum_b sum_{m <= min(l, mmax-1)} g[b,c',l,m] conj(x[b,c,l,m]),
+ * which is dL/dRe W + i dL/dIm W (the gradient of the spectral-convolution
+ * weights, App. B.4 eq. s2_spectral_conv; PyTorch's complex convention).
+ * g, x: spectral tensors of the plan's shape (device, read); dW: complex64
+ * [lmax][channels][channels] (device, written in full; must alias neither
+ * input).  Timed as kind 5 (channel mix). */
+sht_status sht_channel_mix_weight_grad(sht_plan_t plan, const void* g, const void* x, void* dW,
+                                       void* hip_stream);
+
 /* Kernel timing (diagnostics).  With enable != 0 every later call on the
  * plan records a pair of HIP events on the call's stream around each kernel
  * it launches.  sht_plan_timing_read waits for the recorded events, adds the

@@ -32,7 +32,7 @@ def channel_mix_T(g, W):
     return channel_mix(g, np.conj(np.transpose(W, (0, 2, 1))))
 
 
-def channel_mix_dW(g, x):
+def channel_mix_dW(g, x, degrees=None):
     """Gradient of a real loss with respect to the weights of ``channel_mix``,
     in PyTorch's complex convention (dL/dRe W + i dL/dIm W), from the gradient
     g = dL/dRe y + i dL/dIm y of y = channel_mix(x, W):
@@ -42,14 +42,16 @@ def channel_mix_dW(g, x):
     i.e. per degree the product G_l X_l^H of the (channels x (b, m)) matrices,
     over the stored orders m <= min(l, mmax - 1) to which the filter of
     eq. s2_spectral_conv applies (entries l < m of a spectrum are zero).
-    g, x: complex [B, C, lmax, mmax] -> dW: complex [lmax, C, C]."""
+    g, x: complex [B, C, lmax, mmax] -> dW: complex [lmax, C, C] (with
+    ``degrees``, a list of l: only those, complex [len(degrees), C, C])."""
     g = np.asarray(g, dtype=np.complex128)
     x = np.asarray(x, dtype=np.complex128)
     B, C, lmax, mmax = x.shape
-    dW = np.zeros((lmax, C, C), dtype=np.complex128)
-    for l in range(lmax):
+    ls = range(lmax) if degrees is None else list(degrees)
+    dW = np.zeros((len(ls), C, C), dtype=np.complex128)
+    for i, l in enumerate(ls):
         mc = min(l + 1, mmax)
         gl = np.transpose(g[:, :, l, :mc], (1, 0, 2)).reshape(C, B * mc)
         xl = np.transpose(x[:, :, l, :mc], (1, 0, 2)).reshape(C, B * mc)
-        dW[l] = gl @ np.conj(xl).T
+        dW[i] = gl @ np.conj(xl).T
     return dW

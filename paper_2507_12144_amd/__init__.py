@@ -130,6 +130,22 @@ class Plan:
                                                1 if adjoint else 0, _stream_ptr(self.device)))
         return out
 
+    def mix_weight_grad(self, g, x, out=None):
+        """Weight gradient of ``mix``: dW[l,c',c] = sum over b and m <= l of
+        g[b,c',l,m] conj(x[b,c,l,m]) (complex64 [lmax, channels, channels])."""
+        d = self.descs[0]
+        C = d.get("channels", 1)
+        self._check(g, torch.complex64, self.spec_shape(), "g")
+        self._check(x, torch.complex64, self.spec_shape(), "x")
+        if out is None:
+            out = torch.empty((d["lmax"], C, C), dtype=torch.complex64, device=self.device)
+        self._check(out, torch.complex64, (d["lmax"], C, C), "dW")
+        _lib.check(_lib.load().sht_channel_mix_weight_grad(self._h, ctypes.c_void_p(g.data_ptr()),
+                                                           ctypes.c_void_p(x.data_ptr()),
+                                                           ctypes.c_void_p(out.data_ptr()),
+                                                           _stream_ptr(self.device)))
+        return out
+
     # ----------------------------------------------------- batching helpers
     def tune(self, cache=None):
         """Autotune the work schedule (sht_plan_tune); returns (candidate, ms),
@@ -198,19 +214,23 @@ class ISHT(torch.autograd.Function):
 
 
 class ChannelMix(torch.autograd.Function):
-    """y = mix_W(x) per degree; backward gives the input gradient W_l^H g
-    (the weights are treated as constants)."""
+    """y = mix_W(x) per degree; backward gives the input gradient W_l^H g and,
+    when W requires it, the weight gradient sum_{b, m <= l} g x^H."""
 
     @staticmethod
     def forward(ctx, x, W, plan):
         ctx.plan = plan
-        ctx.save_for_backward(W)
-        return plan.mix(W, x.contiguous())
+        x = x.contiguous()
+        ctx.save_for_backward(W, x)
+        return plan.mix(W, x)
 
     @staticmethod
     def backward(ctx, g):
-        (W,) = ctx.saved_tensors
-        return ctx.plan.mix(W, g.contiguous(), adjoint=True), None, None
+        W, x = ctx.saved_tensors
+        g = g.contiguous()
+        gx = ctx.plan.mix(W, g, adjoint=True) if ctx.needs_input_grad[0] else None
+        gW = ctx.plan.mix_weight_grad(g, x) if ctx.needs_input_grad[1] else None
+        return gx, gW, None
 
 
 class Graph:

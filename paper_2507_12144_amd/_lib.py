@@ -15,7 +15,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3}
 # every symbol include/sht.h declares
 EXPORTS = ["sht_plan", "sht_plan_destroy", "sht_plan_segment", "sht_plan_sizes", "sht_plan_grid",
            "sht_forward", "isht_forward", "sht_backward", "isht_backward", "sht_channel_mix",
-           "sht_graph_create", "sht_graph_launch", "sht_graph_destroy", "sht_plan_tune",
+           "sht_channel_mix_weight_grad", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy", "sht_plan_tune",
            "sht_plan_timing", "sht_plan_timing_read", "sht_status_string", "sht_last_error"]
 
 OPS = {"sht": 0, "isht": 1, "sht_T": 2, "isht_T": 3}
@@ -57,6 +57,7 @@ def load():
     for name in ("sht_forward", "isht_forward", "sht_backward", "isht_backward"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.sht_channel_mix.argtypes = [vp, vp, vp, vp, ip, vp]
+    lib.sht_channel_mix_weight_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.sht_plan_timing.argtypes = [vp, ip]
     lib.sht_plan_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), ip]
     for name in EXPORTS[:-2]:

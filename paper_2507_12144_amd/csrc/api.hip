@@ -606,6 +606,21 @@ sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void*
   return SHT_OK;
 }
 
+sht_status sht_channel_mix_weight_grad(sht_plan_t plan, const void* g, const void* x, void* dW,
+                                       void* hip_stream) {
+  if (!plan || !g || !x || !dW) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (dW == g || dW == x) return fail(SHT_ERR_INVALID_ARG, "dW must alias neither input");
+  if (plan->segs.size() != 1) return fail(SHT_ERR_INVALID_ARG, "channel mix needs a single-segment plan");
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_MIX, st, [&] {
+    return launch_channel_mix_weight_grad(d.batch, d.channels, d.lmax, d.mmax, static_cast<const float2*>(g),
+                                          static_cast<const float2*>(x), static_cast<float2*>(dW), st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "channel mix weight gradient launch");
+  return SHT_OK;
+}
+
 sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const void* const* inputs,
                             void* const* outputs, sht_graph_t* out) {
   if (!out) return fail(SHT_ERR_INVALID_ARG, "out is NULL");

@@ -111,6 +111,9 @@ hipError_t launch_legendre_analysis_bf16_batched(const BatchArgs& b, int planes,
 hipError_t launch_legendre_synthesis_bf16_batched(const BatchArgs& b, int planes, const float2* y, hipStream_t st);
 
 // ---- mix.hip -------------------------------------------------------------
+// dW[l][c'][c] = sum_{b, m <= min(l, mmax-1)} g[b][c'][l][m] conj(x[b][c][l][m])
+hipError_t launch_channel_mix_weight_grad(int batch, int channels, int lmax, int mmax, const float2* g,
+                                          const float2* x, float2* dW, hipStream_t stream);
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
                               const float2* in, float2* out, int adjoint, hipStream_t stream);
 

@@ -92,7 +92,71 @@ __global__ void mix_zero_kernel(int B, int C, int lmax, int mmax, float2* __rest
   }
 }
 
+// Weight gradient of the mix: dW[l, c', c] = sum_{b, m <= l} g[b, c', l, m]
+// conj(x[b, c, l, m]), per degree the complex GEMM G_l (C x K) X_l^H (K x C)
+// over the K = B * (l + 1) columns (b, m) with m <= min(l, mmax - 1).  A
+// workgroup computes a 32 x 32 tile (rows c', columns c) through 16-deep
+// LDS-staged slices of K; each thread owns a 2 x 2 block of outputs.  The
+// slices are loaded with consecutive threads on consecutive orders m.
+__global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int lmax, int mmax,
+                                                              const float2* __restrict__ g,
+                                                              const float2* __restrict__ x,
+                                                              float2* __restrict__ dW) {
+  __shared__ float2 sG[KT][MT + 1];
+  __shared__ float2 sX[KT][NT + 1];
+  const int l = blockIdx.z;
+  const int mcount = (l + 1 < mmax) ? l + 1 : mmax;
+  const int K = B * mcount;
+  const int r0 = blockIdx.y * MT;  // output rows c'
+  const int q0 = blockIdx.x * NT;  // output columns c
+  const int tid = threadIdx.x;
+  const int tr = tid / 16, tc = tid % 16;
+  float2 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < K; k0 += KT) {
+    for (int e = tid; e < KT * MT; e += 256) {
+      const int i = e / KT, kk = e % KT;  // consecutive threads: consecutive k
+      const int k = k0 + kk;
+      const int b = k / mcount, m = k - (k / mcount) * mcount;
+      float2 vg = make_float2(0.f, 0.f), vx = vg;
+      if (k < K) {
+        if (r0 + i < C) vg = g[((static_cast<size_t>(b) * C + r0 + i) * lmax + l) * mmax + m];
+        if (q0 + i < C) vx = x[((static_cast<size_t>(b) * C + q0 + i) * lmax + l) * mmax + m];
+      }
+      sG[kk][i] = vg;
+      sX[kk][i] = vx;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < KT; ++kk) {
+      float2 gv[2], xv[2];
+      for (int i = 0; i < 2; ++i) gv[i] = sG[kk][tr + 16 * i];
+      for (int j = 0; j < 2; ++j) xv[j] = sX[kk][tc + 16 * j];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {  // g * conj(x)
+          acc[i][j].x += gv[i].x * xv[j].x + gv[i].y * xv[j].y;
+          acc[i][j].y += gv[i].y * xv[j].x - gv[i].x * xv[j].y;
+        }
+    }
+    __syncthreads();
+  }
+  const size_t wl = static_cast<size_t>(l) * C * C;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int co = r0 + tr + 16 * i, ci = q0 + tc + 16 * j;
+      if (co < C && ci < C) dW[wl + static_cast<size_t>(co) * C + ci] = acc[i][j];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_channel_mix_weight_grad(int batch, int channels, int lmax, int mmax, const float2* g,
+                                          const float2* x, float2* dW, hipStream_t stream) {
+  static_assert(MT == NT, "square tiles: the slice loader shares its index for rows and columns");
+  dim3 grid((channels + NT - 1) / NT, (channels + MT - 1) / MT, lmax);
+  hipLaunchKernelGGL(mix_weight_grad_kernel, grid, dim3(256), 0, stream, batch, channels, lmax, mmax, g, x, dW);
+  return hipGetLastError();
+}
 
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
                               const float2* in, float2* out, int adjoint, hipStream_t stream) {

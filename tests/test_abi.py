@@ -101,6 +101,7 @@ def test_null_plan_calls(lib):
     assert lib.sht_plan_segment(None, 0, ctypes.byref(a), ctypes.byref(b)) == 1
     assert lib.sht_plan_sizes(None, ctypes.byref(a), ctypes.byref(b)) == 1
     assert lib.sht_channel_mix(None, None, None, None, 0, None) == 1
+    assert lib.sht_channel_mix_weight_grad(None, None, None, None, None) == 1
     g = ctypes.c_void_p(1)
     assert lib.sht_graph_create(None, 1, None, None, None, ctypes.byref(g)) == 1
     assert g.value is None  # cleared before the argument checks fail
