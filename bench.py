@@ -40,7 +40,7 @@ def parse():
                     help="only copy a 256 MiB device buffer three times (reference kernel for HBM counters)")
     ap.add_argument("--cpu-fields", type=int, default=72,
                     help="fields in the oracle's timed sample (of the 72)")
-    ap.add_argument("--workload", default="sht721", choices=["sht721", "batched"],
+    ap.add_argument("--workload", default="sht721", choices=["sht721", "batched", "sfno_block"],
                     help="sht721: the headline single-grid step; batched: uneven grids in one plan, "
                          "graph-replayed, with p50/p99 replay latency")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batched workload)")
@@ -166,16 +166,91 @@ def batched_bench(args):
     plan.close()
 
 
+def sfno_block_bench(args):
+    """The spectral-convolution block y = ISHT(mix_W(SHT(x))) on a Gauss
+    360 x 720 grid, lmax = mmax = 360, 4 x 256 channels, forward and backward
+    with the weight gradient: SHT, mix, ISHT, then ISHT^T, mix^T, dW, SHT^T
+    (FP32).  Per-kernel times from HIP events on the launch stream; the
+    roofline of the channel-mix kernels (mix, mix^T and dW: per launch
+    8 C^2 sum_l B min(l + 1, mmax) flops) is against the FP32 vector peak."""
+    import numpy as np
+    import torch
+    import paper_2507_12144_amd as P
+    torch.cuda.set_device(0)
+    nlat, nlon, L, B, C = 360, 720, 360, 4, 256
+    plan = P.Plan(dict(nlat=nlat, nlon=nlon, lmax=L, mmax=L, grid="gauss", batch=B, channels=C))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    x = torch.randn(plan.grid_shape(), device="cuda", generator=gen)
+    r = torch.randn(plan.grid_shape(), device="cuda", generator=gen)
+    W = (torch.randn((L, C, C), device="cuda", generator=gen)
+         + 1j * torch.randn((L, C, C), device="cuda", generator=gen)).to(torch.complex64) / (2 * C) ** 0.5
+    y = torch.empty(plan.spec_shape(), dtype=torch.complex64, device="cuda")
+    z, gz, gy = torch.empty_like(y), torch.empty_like(y), torch.empty_like(y)
+    u, gx = torch.empty_like(x), torch.empty_like(x)
+    dW = torch.empty_like(W)
+
+    def step():
+        plan.sht(x, out=y)
+        plan.mix(W, y, out=z)
+        plan.isht(z, out=u)
+        plan.isht_T(r, out=gz)
+        plan.mix(W, gz, adjoint=True, out=gy)
+        plan.mix_weight_grad(gz, y, out=dW)
+        plan.sht_T(gy, out=gx)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.read_timing()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = plan.read_timing()
+    plan.set_timing(False)
+    avg = {k: 1000.0 * v[0] / v[1] for k, v in kt.items() if v[1]}
+    mix_flops = 8.0 * C * C * sum(B * min(l + 1, L) for l in range(L))
+    mix_us = avg.get("channel_mix", float("nan"))
+    achieved = mix_flops / (mix_us * 1e-6) / 1e12
+    peak = PEAKS_TFLOPS["fp32"]
+    F = B * C
+    out = {
+        "metric": "spectral-convolution block fwd+bwd (SHT, per-degree channel mix, ISHT, adjoints, weight "
+                  "gradient) fields/sec",
+        "value": round(F * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Gauss 360x720, lmax=mmax=360, batch 4 x 256 channels; SHT -> mix_W -> ISHT "
+                               "then ISHT^T -> mix_W^H and dW -> SHT^T",
+                   "nlat": nlat, "nlon": nlon, "lmax": L, "mmax": L, "fields": F, "channels": C},
+        "roofline": {"bound": "alu", "kernel": "channel_mix (mix, mix^H, dW)", "achieved": round(achieved, 2),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "avg_launch_us": round(mix_us, 2), "algorithmic_flops_per_launch": mix_flops},
+        "cpu_baseline": None,
+        "gpu_event_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 4),
+        "kernel_avg_us": {k: round(v, 2) for k, v in avg.items()},
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload == "batched":
+    if args.workload in ("batched", "sfno_block"):
         if args.gpus != 1:
             print("bench.py: this build measures one GPU only", file=sys.stderr, flush=True)
             sys.exit(2)
-        batched_bench(args)
+        (batched_bench if args.workload == "batched" else sfno_block_bench)(args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
