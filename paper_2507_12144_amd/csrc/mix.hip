@@ -4,15 +4,16 @@
 // l only, never on m).
 //
 // For each degree l this is a complex GEMM  W_l (C x C) @ X_l (C x B*(l+1)),
-// columns (b, m) with m <= min(l, mmax-1).  A workgroup computes a 32 x 32
-// output tile through 16-deep LDS-staged slices; each thread owns a 2 x 2
-// block of complex outputs.
+// columns (b, m) with m <= min(l, mmax-1).  A workgroup computes a 64 x 64
+// output tile through 16-deep LDS-staged slices; each thread owns a 4 x 4
+// block of complex outputs (eight LDS values feed 16 complex products).
 #include "internal.h"
 
 namespace sht {
 namespace {
 
-constexpr int MT = 32, NT = 32, KT = 16;
+constexpr int MT = 64, NT = 64, KT = 16;  // output tile and K slice
+constexpr int RT = 4;                     // outputs per thread along each tile side
 
 __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax, int mmax,
                                                           const float2* __restrict__ W,
@@ -27,14 +28,16 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
   const int j0 = blockIdx.x * NT;   // (b, m) column tile
   if (j0 >= ncols) return;
   const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;  // 16 x 16 threads, 2 x 2 outputs each
-  float2 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  const int tr = tid / 16, tc = tid % 16;  // 16 x 16 threads, RT x RT outputs each
+  float2 acc[RT][RT];
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < RT; ++j) acc[i][j] = make_float2(0.f, 0.f);
   const size_t wl = static_cast<size_t>(l) * C * C;
   for (int k0 = 0; k0 < C; k0 += KT) {
     for (int e = tid; e < KT * MT; e += 256) {
-      const int kk = e / MT, i = e % MT;
+      // consecutive threads on consecutive addresses: along c for W_l,
+      // along c' for W_l^H
+      const int kk = adjoint ? e / MT : e % KT, i = adjoint ? e % MT : e / KT;
       const int co = c0 + i, ci = k0 + kk;
       float2 v = make_float2(0.f, 0.f);
       if (co < C && ci < C) {
@@ -59,19 +62,19 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
     }
     __syncthreads();
     for (int kk = 0; kk < KT; ++kk) {
-      float2 wv[2], xv[2];
-      for (int i = 0; i < 2; ++i) wv[i] = sW[kk][tr + 16 * i];
-      for (int j = 0; j < 2; ++j) xv[j] = sX[kk][tc + 16 * j];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
+      float2 wv[RT], xv[RT];
+      for (int i = 0; i < RT; ++i) wv[i] = sW[kk][tr + 16 * i];
+      for (int j = 0; j < RT; ++j) xv[j] = sX[kk][tc + 16 * j];
+      for (int i = 0; i < RT; ++i)
+        for (int j = 0; j < RT; ++j) {
           acc[i][j].x += wv[i].x * xv[j].x - wv[i].y * xv[j].y;
           acc[i][j].y += wv[i].x * xv[j].y + wv[i].y * xv[j].x;
         }
     }
     __syncthreads();
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < RT; ++j) {
       const int co = c0 + tr + 16 * i;
       const int col = j0 + tc + 16 * j;
       if (co < C && col < ncols) {
@@ -95,8 +98,8 @@ __global__ void mix_zero_kernel(int B, int C, int lmax, int mmax, float2* __rest
 // Weight gradient of the mix: dW[l, c', c] = sum_{b, m <= l} g[b, c', l, m]
 // conj(x[b, c, l, m]), per degree the complex GEMM G_l (C x K) X_l^H (K x C)
 // over the K = B * (l + 1) columns (b, m) with m <= min(l, mmax - 1).  A
-// workgroup computes a 32 x 32 tile (rows c', columns c) through 16-deep
-// LDS-staged slices of K; each thread owns a 2 x 2 block of outputs.  The
+// workgroup computes a 64 x 64 tile (rows c', columns c) through 16-deep
+// LDS-staged slices of K; each thread owns a 4 x 4 block of outputs.  The
 // slices are loaded with consecutive threads on consecutive orders m.
 __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int lmax, int mmax,
                                                               const float2* __restrict__ g,
@@ -111,9 +114,9 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
   const int q0 = blockIdx.x * NT;  // output columns c
   const int tid = threadIdx.x;
   const int tr = tid / 16, tc = tid % 16;
-  float2 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  float2 acc[RT][RT];
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < RT; ++j) acc[i][j] = make_float2(0.f, 0.f);
   for (int k0 = 0; k0 < K; k0 += KT) {
     for (int e = tid; e < KT * MT; e += 256) {
       const int i = e / KT, kk = e % KT;  // consecutive threads: consecutive k
@@ -129,11 +132,11 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
     }
     __syncthreads();
     for (int kk = 0; kk < KT; ++kk) {
-      float2 gv[2], xv[2];
-      for (int i = 0; i < 2; ++i) gv[i] = sG[kk][tr + 16 * i];
-      for (int j = 0; j < 2; ++j) xv[j] = sX[kk][tc + 16 * j];
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {  // g * conj(x)
+      float2 gv[RT], xv[RT];
+      for (int i = 0; i < RT; ++i) gv[i] = sG[kk][tr + 16 * i];
+      for (int j = 0; j < RT; ++j) xv[j] = sX[kk][tc + 16 * j];
+      for (int i = 0; i < RT; ++i)
+        for (int j = 0; j < RT; ++j) {  // g * conj(x)
           acc[i][j].x += gv[i].x * xv[j].x + gv[i].y * xv[j].y;
           acc[i][j].y += gv[i].y * xv[j].x - gv[i].x * xv[j].y;
         }
@@ -141,8 +144,8 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
     __syncthreads();
   }
   const size_t wl = static_cast<size_t>(l) * C * C;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < RT; ++j) {
       const int co = r0 + tr + 16 * i, ci = q0 + tc + 16 * j;
       if (co < C && ci < C) dW[wl + static_cast<size_t>(co) * C + ci] = acc[i][j];
     }
