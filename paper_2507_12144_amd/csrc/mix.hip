@@ -5,15 +5,66 @@
 //
 // For each degree l this is a complex GEMM  W_l (C x C) @ X_l (C x B*(l+1)),
 // columns (b, m) with m <= min(l, mmax-1).  A workgroup computes a 64 x 64
-// output tile through 16-deep LDS-staged slices; each thread owns a 4 x 4
-// block of complex outputs (eight LDS values feed 16 complex products).
+// output tile through 16-deep LDS-staged slices on the FP32 matrix cores
+// (ComplexTile).
 #include "internal.h"
 
 namespace sht {
 namespace {
 
 constexpr int MT = 64, NT = 64, KT = 16;  // output tile and K slice
-constexpr int RT = 4;                     // outputs per thread along each tile side
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Complex 64 x 64 output tile on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32): wave w owns the 32 x 32 sub-tile at rows
+// 32 (w / 2), columns 32 (w % 2), i.e. 2 x 2 blocks of 16 x 16; per 4-deep
+// step of the K slice a block takes four real products,
+// re += a_re b_re - a_im b_im and im += a_re b_im + a_im b_re.  Lane
+// (li = lane % 16, lk = lane / 16) supplies A[row li][k lk] and B[k lk][col
+// li] and receives C[row 4 lk + r][col li], r < 4.
+struct ComplexTile {
+  floatx4 re[2][2], im[2][2];
+  __device__ __forceinline__ void zero() {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) re[i][j] = im[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  }
+  // sA[k][p], sB[k][q]: the current K slice of the two operands
+  __device__ __forceinline__ void step(const float2 (*sA)[MT + 1], const float2 (*sB)[NT + 1]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int k4 = 0; k4 < KT; k4 += 4) {
+      float2 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = sA[k4 + lk][pr + 16 * t + li];
+        b[t] = sB[k4 + lk][qc + 16 * t + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, re[i][j], 0, 0, 0);
+          re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[i].y, b[j].y, re[i][j], 0, 0, 0);
+          im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].y, im[i][j], 0, 0, 0);
+          im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].x, im[i][j], 0, 0, 0);
+        }
+    }
+  }
+  // f(p, q, value) for every output of this lane (p, q within the tile)
+  template <class F>
+  __device__ __forceinline__ void store(F&& f) const {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pr = (wave >> 1) * 32, qc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r)
+          f(pr + 16 * i + 4 * lk + r, qc + 16 * j + li, make_float2(re[i][j][r], im[i][j][r]));
+  }
+};
 
 __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax, int mmax,
                                                           const float2* __restrict__ W,
@@ -28,10 +79,8 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
   const int j0 = blockIdx.x * NT;   // (b, m) column tile
   if (j0 >= ncols) return;
   const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;  // 16 x 16 threads, RT x RT outputs each
-  float2 acc[RT][RT];
-  for (int i = 0; i < RT; ++i)
-    for (int j = 0; j < RT; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  ComplexTile acc;
+  acc.zero();
   const size_t wl = static_cast<size_t>(l) * C * C;
   for (int k0 = 0; k0 < C; k0 += KT) {
     for (int e = tid; e < KT * MT; e += 256) {
@@ -61,27 +110,16 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
       sX[kk][j] = v;
     }
     __syncthreads();
-    for (int kk = 0; kk < KT; ++kk) {
-      float2 wv[RT], xv[RT];
-      for (int i = 0; i < RT; ++i) wv[i] = sW[kk][tr + 16 * i];
-      for (int j = 0; j < RT; ++j) xv[j] = sX[kk][tc + 16 * j];
-      for (int i = 0; i < RT; ++i)
-        for (int j = 0; j < RT; ++j) {
-          acc[i][j].x += wv[i].x * xv[j].x - wv[i].y * xv[j].y;
-          acc[i][j].y += wv[i].x * xv[j].y + wv[i].y * xv[j].x;
-        }
-    }
+    acc.step(sW, sX);
     __syncthreads();
   }
-  for (int i = 0; i < RT; ++i)
-    for (int j = 0; j < RT; ++j) {
-      const int co = c0 + tr + 16 * i;
-      const int col = j0 + tc + 16 * j;
-      if (co < C && col < ncols) {
-        const int b = col / mcount, m = col % mcount;
-        out[((static_cast<size_t>(b) * C + co) * lmax + l) * mmax + m] = acc[i][j];
-      }
+  acc.store([&](int pi, int qi, float2 v) {
+    const int co = c0 + pi, col = j0 + qi;
+    if (co < C && col < ncols) {
+      const int b = col / mcount, m = col % mcount;
+      out[((static_cast<size_t>(b) * C + co) * lmax + l) * mmax + m] = v;
     }
+  });
 }
 
 // out[b, c, l, m] = 0 for m > l (the part the mix kernel never writes).
@@ -99,7 +137,7 @@ __global__ void mix_zero_kernel(int B, int C, int lmax, int mmax, float2* __rest
 // conj(x[b, c, l, m]), per degree the complex GEMM G_l (C x K) X_l^H (K x C)
 // over the K = B * (l + 1) columns (b, m) with m <= min(l, mmax - 1).  A
 // workgroup computes a 64 x 64 tile (rows c', columns c) through 16-deep
-// LDS-staged slices of K; each thread owns a 4 x 4 block of outputs.  The
+// LDS-staged slices of K on the matrix cores (ComplexTile).  The
 // slices are loaded with consecutive threads on consecutive orders m.
 __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int lmax, int mmax,
                                                               const float2* __restrict__ g,
@@ -113,10 +151,8 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
   const int r0 = blockIdx.y * MT;  // output rows c'
   const int q0 = blockIdx.x * NT;  // output columns c
   const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  float2 acc[RT][RT];
-  for (int i = 0; i < RT; ++i)
-    for (int j = 0; j < RT; ++j) acc[i][j] = make_float2(0.f, 0.f);
+  ComplexTile acc;
+  acc.zero();
   for (int k0 = 0; k0 < K; k0 += KT) {
     for (int e = tid; e < KT * MT; e += 256) {
       const int i = e / KT, kk = e % KT;  // consecutive threads: consecutive k
@@ -128,27 +164,17 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
         if (q0 + i < C) vx = x[((static_cast<size_t>(b) * C + q0 + i) * lmax + l) * mmax + m];
       }
       sG[kk][i] = vg;
-      sX[kk][i] = vx;
+      sX[kk][i] = make_float2(vx.x, -vx.y);  // B = X^H
     }
     __syncthreads();
-    for (int kk = 0; kk < KT; ++kk) {
-      float2 gv[RT], xv[RT];
-      for (int i = 0; i < RT; ++i) gv[i] = sG[kk][tr + 16 * i];
-      for (int j = 0; j < RT; ++j) xv[j] = sX[kk][tc + 16 * j];
-      for (int i = 0; i < RT; ++i)
-        for (int j = 0; j < RT; ++j) {  // g * conj(x)
-          acc[i][j].x += gv[i].x * xv[j].x + gv[i].y * xv[j].y;
-          acc[i][j].y += gv[i].y * xv[j].x - gv[i].x * xv[j].y;
-        }
-    }
+    acc.step(sG, sX);
     __syncthreads();
   }
   const size_t wl = static_cast<size_t>(l) * C * C;
-  for (int i = 0; i < RT; ++i)
-    for (int j = 0; j < RT; ++j) {
-      const int co = r0 + tr + 16 * i, ci = q0 + tc + 16 * j;
-      if (co < C && ci < C) dW[wl + static_cast<size_t>(co) * C + ci] = acc[i][j];
-    }
+  acc.store([&](int pi, int qi, float2 v) {
+    const int co = r0 + pi, ci = q0 + qi;
+    if (co < C && ci < C) dW[wl + static_cast<size_t>(co) * C + ci] = v;
+  });
 }
 
 }  // namespace
