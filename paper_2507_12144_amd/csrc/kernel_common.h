@@ -23,6 +23,11 @@ namespace sht {
 // this wave are outstanding (expcnt and lgkmcnt left at their maxima).
 constexpr int vm_wait(int n) { return 0x0F70 | (n & 15) | (((n >> 4) & 3) << 14); }
 
+// Wait for vector memory (at most n copies of this wave in flight) and for
+// every LDS read of this wave, so that after the barrier that follows no
+// wave still reads a buffer the next copies overwrite.
+constexpr int vm_lds_wait(int n) { return vm_wait(n) & ~0x0F00; }
+
 // Workgroup barrier for LDS filled by asynchronous global->LDS copies.  The
 // caller first waits (vm_wait) for its own copies of the stage; the barrier
 // then makes every wave's copies visible.  The empty asm statements keep the

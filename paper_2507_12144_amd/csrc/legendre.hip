@@ -123,7 +123,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
   if (nb > 0) {
     // Every stage issues the copies of stage s+2, past the end too, so that
     // each wave always has exactly LPW copies in flight behind the ones it
-    // waits for and every wait is the same vm_wait(LPW).
+    // waits for and every wait is the same vm_lds_wait(LPW).
     constexpr int XS = S::XS;
     if constexpr (S::XSTREAM) {
       // Stage u < XS: every wave copies rings lk * KS + 16u .. +15 of its
@@ -144,7 +144,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
         constexpr int u = decltype(u_c)::value;
         v4f* cur = ring_buf<u>(b0, b1, b2);
         v4f* nxt = ring_buf<u + 2>(b0, b1, b2);
-        __builtin_amdgcn_s_waitcnt(vm_wait(u + 1 < XS ? S::LPWX : LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(u + 1 < XS ? S::LPWX : LPW));
         stage_barrier();
         if constexpr (u + 2 < XS)
           issue_x(nxt, u + 2);
@@ -168,7 +168,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
         if (st >= nst) return false;
         v4f* cur = ring_buf<su + XS>(b0, b1, b2);
         v4f* nxt = ring_buf<su + XS + 2>(b0, b1, b2);
-        __builtin_amdgcn_s_waitcnt(vm_wait(LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(LPW));
         stage_barrier();
         issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
         const int ib = st / PARTS;
@@ -293,7 +293,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         constexpr int pm2 = (part + 2 * PARTS - 2) % PARTS, pm1 = (part + PARTS - 1) % PARTS;
         constexpr int behind = LPW + (pm2 == 1 ? 4 : 0) + (pm1 == 1 ? 4 : 0);
         constexpr int need = (part == 0 && (PARTS - 2) * LPW < behind) ? (PARTS - 2) * LPW : behind;
-        __builtin_amdgcn_s_waitcnt(vm_wait(need) & ~0x0F00);  // and every LDS read of this wave
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(need));
         stage_barrier();
         const int ib = st / PARTS;
         if constexpr (part == 0) {

@@ -126,11 +126,6 @@ __device__ __forceinline__ void issue_stage(v4f* B, const uint16_t* __restrict__
 
 __device__ __forceinline__ bf16x8 as_bf16x8(v4f v) { return __builtin_bit_cast(bf16x8, v); }
 
-// Wait for vector memory (at most n copies of this wave in flight) and for
-// every LDS read of this wave, so that after the barrier that follows no
-// wave still reads a buffer the next copies overwrite.
-constexpr int vm_lds_wait(int n) { return vm_wait(n) & ~0x0F00; }
-
 // Copies per wave in flight behind global analysis stage gs: those of
 // stages gs+1 .. gs+D-1 (four for a stage of S / A, LPW for a table stage).
 template <int XS, int LPW, int D>
