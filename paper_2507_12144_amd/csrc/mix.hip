@@ -82,8 +82,16 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
   ComplexTile acc;
   acc.zero();
   const size_t wl = static_cast<size_t>(l) * C * C;
-  for (int k0 = 0; k0 < C; k0 += KT) {
-    for (int e = tid; e < KT * MT; e += 256) {
+  // The slice k0 .. k0+KT-1 of both operands, PER values a thread, held in
+  // registers: the next slice's loads are in flight while the matrix cores
+  // work on the current one.
+  constexpr int PER = KT * MT / 256;
+  static_assert(KT * MT == KT * NT && KT * MT % 256 == 0, "slice split");
+  float2 pw[PER], px[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
       // consecutive threads on consecutive addresses: along c for W_l,
       // along c' for W_l^H
       const int kk = adjoint ? e / MT : e % KT, i = adjoint ? e % MT : e / KT;
@@ -97,19 +105,31 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
           v = W[wl + static_cast<size_t>(co) * C + ci];
         }
       }
-      sW[kk][i] = v;
-    }
-    for (int e = tid; e < KT * NT; e += 256) {
-      const int kk = e / NT, j = e % NT;
-      const int col = j0 + j, ci = k0 + kk;
-      float2 v = make_float2(0.f, 0.f);
-      if (col < ncols && ci < C) {
+      pw[q] = v;
+      const int xk = e / NT, j = e % NT;
+      const int col = j0 + j, xi = k0 + xk;
+      float2 u = make_float2(0.f, 0.f);
+      if (col < ncols && xi < C) {
         const int b = col / mcount, m = col % mcount;
-        v = in[((static_cast<size_t>(b) * C + ci) * lmax + l) * mmax + m];
+        u = in[((static_cast<size_t>(b) * C + xi) * lmax + l) * mmax + m];
       }
-      sX[kk][j] = v;
+      px[q] = u;
     }
+  };
+  auto place = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = adjoint ? e / MT : e % KT, i = adjoint ? e % MT : e / KT;
+      sW[kk][i] = pw[q];
+      sX[e / NT][e % NT] = px[q];
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < C; k0 += KT) {
+    place();
     __syncthreads();
+    if (k0 + KT < C) load(k0 + KT);
     acc.step(sW, sX);
     __syncthreads();
   }
@@ -153,8 +173,14 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
   const int tid = threadIdx.x;
   ComplexTile acc;
   acc.zero();
-  for (int k0 = 0; k0 < K; k0 += KT) {
-    for (int e = tid; e < KT * MT; e += 256) {
+  // slices held in registers, the next one loading during the current
+  // one's matrix-core work (as in the mix kernel)
+  constexpr int PER = KT * MT / 256;
+  float2 pg[PER], px[PER];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
       const int i = e / KT, kk = e % KT;  // consecutive threads: consecutive k
       const int k = k0 + kk;
       const int b = k / mcount, m = k - (k / mcount) * mcount;
@@ -163,10 +189,20 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
         if (r0 + i < C) vg = g[((static_cast<size_t>(b) * C + r0 + i) * lmax + l) * mmax + m];
         if (q0 + i < C) vx = x[((static_cast<size_t>(b) * C + q0 + i) * lmax + l) * mmax + m];
       }
-      sG[kk][i] = vg;
-      sX[kk][i] = make_float2(vx.x, -vx.y);  // B = X^H
+      pg[q] = vg;
+      px[q] = make_float2(vx.x, -vx.y);  // B = X^H
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KT) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      sG[e % KT][e / KT] = pg[q];
+      sX[e % KT][e / KT] = px[q];
     }
     __syncthreads();
+    if (k0 + KT < K) load(k0 + KT);
     acc.step(sG, sX);
     __syncthreads();
   }
