@@ -16,6 +16,20 @@ constexpr int MT = 64, NT = 64, KT = 16;  // output tile and K slice
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Workgroup -> (degree l, tile) with every tile of a degree on one XCD (the
+// hardware deals workgroup b to XCD b % 8), so that the operands of degree l
+// are fetched into one L2: degree l goes to XCD l % 8 (the work of a degree
+// grows with l, so this balances the XCDs), its T tiles run consecutively
+// there.  The grid has 8 * ceil(lmax / 8) * T workgroups.
+struct DegreeTile {
+  int l, tile;
+  __device__ __forceinline__ DegreeTile(int T) {
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    l = xcd + 8 * (slot / T);
+    tile = slot % T;
+  }
+};
+
 // Complex 64 x 64 output tile on the FP32 matrix cores
 // (v_mfma_f32_16x16x4_f32): wave w owns the 32 x 32 sub-tile at rows
 // 32 (w / 2), columns 32 (w % 2), i.e. 2 x 2 blocks of 16 x 16; per 4-deep
@@ -72,11 +86,14 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
                                                           float2* __restrict__ out, int adjoint) {
   __shared__ float2 sW[KT][MT + 1];
   __shared__ float2 sX[KT][NT + 1];
-  const int l = blockIdx.z;
+  const int tx = (B * mmax + NT - 1) / NT, ty = (C + MT - 1) / MT;
+  const DegreeTile dt(tx * ty);
+  const int l = dt.l;
+  if (l >= lmax) return;
   const int mcount = (l + 1 < mmax) ? l + 1 : mmax;  // orders m <= l
   const int ncols = B * mcount;
-  const int c0 = blockIdx.y * MT;   // output channel tile
-  const int j0 = blockIdx.x * NT;   // (b, m) column tile
+  const int c0 = (dt.tile / tx) * MT;   // output channel tile
+  const int j0 = (dt.tile % tx) * NT;   // (b, m) column tile
   if (j0 >= ncols) return;
   const int tid = threadIdx.x;
   ComplexTile acc;
@@ -165,11 +182,14 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
                                                               float2* __restrict__ dW) {
   __shared__ float2 sG[KT][MT + 1];
   __shared__ float2 sX[KT][NT + 1];
-  const int l = blockIdx.z;
+  const int tq = (C + NT - 1) / NT, tr = (C + MT - 1) / MT;
+  const DegreeTile dt(tq * tr);
+  const int l = dt.l;
+  if (l >= lmax) return;
   const int mcount = (l + 1 < mmax) ? l + 1 : mmax;
   const int K = B * mcount;
-  const int r0 = blockIdx.y * MT;  // output rows c'
-  const int q0 = blockIdx.x * NT;  // output columns c
+  const int r0 = (dt.tile / tq) * MT;  // output rows c'
+  const int q0 = (dt.tile % tq) * NT;  // output columns c
   const int tid = threadIdx.x;
   ComplexTile acc;
   acc.zero();
@@ -218,15 +238,20 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
 hipError_t launch_channel_mix_weight_grad(int batch, int channels, int lmax, int mmax, const float2* g,
                                           const float2* x, float2* dW, hipStream_t stream) {
   static_assert(MT == NT, "square tiles: the slice loader shares its index for rows and columns");
-  dim3 grid((channels + NT - 1) / NT, (channels + MT - 1) / MT, lmax);
+  const long long tiles = static_cast<long long>((channels + NT - 1) / NT) * ((channels + MT - 1) / MT);
+  const long long blocks = 8LL * ((lmax + 7) / 8) * tiles;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(blocks));
   hipLaunchKernelGGL(mix_weight_grad_kernel, grid, dim3(256), 0, stream, batch, channels, lmax, mmax, g, x, dW);
   return hipGetLastError();
 }
 
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
                               const float2* in, float2* out, int adjoint, hipStream_t stream) {
-  const int maxcols = batch * mmax;
-  dim3 grid((maxcols + NT - 1) / NT, (channels + MT - 1) / MT, lmax);
+  const long long tiles = static_cast<long long>((batch * mmax + NT - 1) / NT) * ((channels + MT - 1) / MT);
+  const long long mix_blocks = 8LL * ((lmax + 7) / 8) * tiles;
+  if (mix_blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(mix_blocks));
   hipLaunchKernelGGL(channel_mix_kernel, grid, dim3(256), 0, stream, batch, channels, lmax, mmax, W, in,
                      out, adjoint);
   hipError_t e = hipGetLastError();
