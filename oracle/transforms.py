@@ -70,7 +70,9 @@ def _legendre_analysis(X, lmax, x, sin_t):
         # (F, nlat) @ (nlat, lmax - m)
         out[m, :, m:].real = Xr[m] @ rows.T
         out[m, :, m:].imag = Xi[m] @ rows.T
-    return np.moveaxis(out, 0, -1).reshape(lead + (lmax, mmax))
+    # returned in C order ([..., l, m], m fastest): later per-degree slicing
+    # of a strided view would touch one memory page per element
+    return np.ascontiguousarray(np.moveaxis(out, 0, -1).reshape(lead + (lmax, mmax)))
 
 
 def _legendre_synthesis(a, nlat, x, sin_t):
