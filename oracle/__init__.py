@@ -19,6 +19,13 @@ What it computes (all in float64 / complex128, plain definitions written out):
 * ``mix``       -- the per-degree complex channel mix (a multi-channel form of
                    the spectral convolution, App. B.4, eq. s2_spectral_conv)
                    and its adjoint.
+* ``scores``    -- ensemble CRPS in its integral, rank and spread-skill forms
+                   (App. D.4), the spectral and spatial CRPS loss terms
+                   (App. E.1) and the angular and zonal power spectral
+                   densities (App. F.7).
+* ``noise``     -- the spherical diffusion process (App. B.7, eq.
+                   spherical_diffusion) with a counter-based Philox4x64-10
+                   generator and Box-Muller normals.
 
 Every function is pinned by tests in ``tests/test_oracle_*.py`` against
 closed forms, library special cases, invariants and brute force; the
@@ -30,10 +37,15 @@ from .grids import (equiangular_nodes, gauss_legendre, clenshaw_curtis_weights,
 from .legendre import legendre_order, legendre_table
 from .transforms import sht, isht, sht_T, isht_T, sht_bruteforce, isht_bruteforce
 from .mix import channel_mix, channel_mix_T, channel_mix_dW
+from .scores import (crps_integral, crps_sorted, crps_spread_skill, spectral_crps, spatial_crps,
+                     psd, zonal_psd)
+from .noise import philox4x64_10, normal_pairs, diffusion_params, diffusion_step
 
 __all__ = [
     "equiangular_nodes", "gauss_legendre", "clenshaw_curtis_weights",
     "trapezoid_weights", "grid", "legendre_order", "legendre_table",
     "sht", "isht", "sht_T", "isht_T", "sht_bruteforce", "isht_bruteforce",
     "channel_mix", "channel_mix_T", "channel_mix_dW",
+    "crps_integral", "crps_sorted", "crps_spread_skill", "spectral_crps", "spatial_crps", "psd", "zonal_psd",
+    "philox4x64_10", "normal_pairs", "diffusion_params", "diffusion_step",
 ]
