@@ -38,7 +38,7 @@ from .legendre import legendre_order, legendre_table
 from .transforms import sht, isht, sht_T, isht_T, sht_bruteforce, isht_bruteforce
 from .mix import channel_mix, channel_mix_T, channel_mix_dW
 from .scores import (crps_integral, crps_sorted, crps_spread_skill, spectral_crps, spatial_crps,
-                     psd, zonal_psd)
+                     psd, zonal_psd, crps_spread_skill_grad, spectral_crps_grad, spatial_crps_grad)
 from .noise import philox4x64_10, normal_pairs, diffusion_params, diffusion_step
 
 __all__ = [
@@ -47,5 +47,6 @@ __all__ = [
     "sht", "isht", "sht_T", "isht_T", "sht_bruteforce", "isht_bruteforce",
     "channel_mix", "channel_mix_T", "channel_mix_dW",
     "crps_integral", "crps_sorted", "crps_spread_skill", "spectral_crps", "spatial_crps", "psd", "zonal_psd",
+    "crps_spread_skill_grad", "spectral_crps_grad", "spatial_crps_grad",
     "philox4x64_10", "normal_pairs", "diffusion_params", "diffusion_step",
 ]

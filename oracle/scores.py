@@ -23,6 +23,9 @@
 * ``zonal_psd``: eq. zonal_psd, 2 pi sin(t) |integral of u e^{-i m p} dp|^2
   at every ring, the integral taken as the longitude quadrature sum
   (2 pi / nlon) sum_j.
+* ``*_grad``: derivatives of the spread-skill CRPS and of both loss terms
+  with respect to the members (each |.| differentiated as sign(.), with
+  sign(0) = 0), for the backward pass of a training loss.
 
 Readings of the paper (where it is silent or garbled):
 * A spectral coefficient is complex; its CRPS is that of its real part plus
@@ -155,3 +158,43 @@ def zonal_psd(u, kind, mmax):
     theta, _, _ = grid(nlat, kind)
     X = (2.0 * np.pi / nlon) * np.fft.rfft(u, axis=-1)[..., :mmax]
     return 2.0 * np.pi * np.sin(theta)[:, None] * np.abs(X) ** 2
+
+
+def crps_spread_skill_grad(ens, obs, fair=False):
+    """Derivative of ``crps_spread_skill`` with respect to every member:
+    sign(u_e - u*) / N - sum_i sign(u_e - u_i) / N^2 (fair: / N(N - 1)),
+    each |.| differentiated as sign(.) with sign(0) = 0."""
+    ens, obs = _as_ens(ens, obs)
+    n = ens.shape[0]
+    g = np.sign(ens - obs[None]) / n
+    pair = np.zeros_like(ens)
+    for i in range(n):
+        pair += np.sign(ens - ens[i][None])
+    return g - pair / (n * (n - 1) if fair else n * n)
+
+
+def spectral_crps_grad(ens_coeffs, obs_coeffs, nlat, fair=False, l_hi=None):
+    """Gradient of sum(spectral_crps(...)) with respect to the ensemble
+    coefficients in PyTorch's complex convention, dL/dRe + i dL/dIm:
+    complex [N, ..., lmax, mmax]."""
+    ens = np.asarray(ens_coeffs, dtype=np.complex128)
+    obs = np.asarray(obs_coeffs, dtype=np.complex128)
+    lmax, mmax = obs.shape[-2], obs.shape[-1]
+    if l_hi is None:
+        l_hi = min(lmax - 1, nlat // 2)
+    l = np.arange(lmax)[:, None]
+    m = np.arange(mmax)[None, :]
+    w = np.where((l >= 1) & (l <= l_hi) & (m <= l), _order_weights(mmax)[None, :], 0.0)
+    return w * (crps_spread_skill_grad(ens.real, obs.real, fair)
+                + 1j * crps_spread_skill_grad(ens.imag, obs.imag, fair))
+
+
+def spatial_crps_grad(ens_fields, obs_field, kind, fair=False):
+    """Gradient of sum(spatial_crps(...)) with respect to the members' grid
+    values: [N, ..., nlat, nlon]."""
+    ens = np.asarray(ens_fields, dtype=np.float64)
+    obs = np.asarray(obs_field, dtype=np.float64)
+    nlat, nlon = obs.shape[-2], obs.shape[-1]
+    _, _, w = grid(nlat, kind)
+    quad = (2.0 * np.pi / nlon) * w[:, None] * np.ones((1, nlon)) / (4.0 * np.pi)
+    return quad * crps_spread_skill_grad(ens, obs, fair)

@@ -220,3 +220,34 @@ def test_planted_mistakes_are_caught():
     _, _, w = oracle.grid(nlat, 1)
     integral = np.sum(u ** 2 * ((2 * np.pi / nlon) * w)[:, None])
     assert not np.isclose(np.sum(np.abs(a) ** 2), integral, rtol=1e-6)
+
+
+@pytest.mark.parametrize("fair", [False, True])
+def test_crps_gradients_against_central_differences(fair):
+    """The scores are piecewise linear in the members: central differences
+    with a step far below the gap to the nearest kink are exact up to
+    rounding."""
+    nlat, L, M, N = 12, 8, 6, 4
+    rng = np.random.default_rng(7)
+    ens = np.stack([synth.coefficients(40 + e, 1, 2, L, M) for e in range(N)])
+    obs = synth.coefficients(50, 1, 2, L, M)
+    g = S.spectral_crps_grad(ens, obs, nlat, fair=fair)
+    h = 1e-7
+    for _ in range(12):
+        idx = (int(rng.integers(N)), 0, int(rng.integers(2)), int(rng.integers(1, L)), int(rng.integers(M)))
+        for part in (1.0, 1j):
+            d = np.zeros_like(ens)
+            d[idx] = part * h
+            fd = (S.spectral_crps(ens + d, obs, nlat, fair).sum() - S.spectral_crps(ens - d, obs, nlat, fair).sum()) / (2 * h)
+            ref = g[idx].real if part == 1.0 else g[idx].imag
+            assert fd == pytest.approx(ref, abs=1e-6)
+    nlon = 16
+    ens_g = rng.standard_normal((N, 2, nlat, nlon))
+    obs_g = rng.standard_normal((2, nlat, nlon))
+    gg = S.spatial_crps_grad(ens_g, obs_g, 0, fair)
+    for _ in range(12):
+        idx = tuple(int(rng.integers(s)) for s in ens_g.shape)
+        d = np.zeros_like(ens_g)
+        d[idx] = h
+        fd = (S.spatial_crps(ens_g + d, obs_g, 0, fair).sum() - S.spatial_crps(ens_g - d, obs_g, 0, fair).sum()) / (2 * h)
+        assert fd == pytest.approx(gg[idx], abs=1e-8)
