@@ -76,8 +76,11 @@ typedef enum {
 typedef enum {
     SHT_PREC_FP32 = 0,   /* float32 table and data, float32 MFMA            */
     SHT_PREC_BF16 = 1,   /* bfloat16 table and data, bf16 MFMA, fp32 accum   */
-    SHT_PREC_BF16X2 = 2, /* split bf16: v = hi + lo for table and data,
-                            products hi*hi + hi*lo + lo*hi, fp32 accumulate  */
+    SHT_PREC_BF16X2 = 2, /* split bf16: the table stored as hi + lo bf16
+                            planes (hi = bf16(v), lo = bf16(v - hi)), the
+                            data split in registers into three bf16 terms
+                            d0 + d1 + d2; products t0 d0 + t0 d1 + t1 d0 +
+                            t0 d2 + t1 d1, fp32 accumulate               */
     SHT_PREC_BF16X3 = 3  /* three-term bf16 split of the table and data,
                             the six products of order < 3, fp32 accumulate  */
 } sht_precision;
@@ -97,7 +100,9 @@ typedef struct sht_plan_s* sht_plan_t;
  * spherical_harmonics), allocates the workspace, and leaves the plan bound to
  * the current HIP device.  hip_stream: the stream used for plan-time work and
  * as the default stream of later calls (NULL: the null stream).
- * *out is set to NULL on failure. */
+ * *out is set to NULL on failure; a failed build frees everything it had
+ * allocated.  Test hook: with SHT_TEST_FAIL_ALLOC=n in the environment the
+ * n-th device allocation of the call fails (SHT_ERR_OUT_OF_MEMORY). */
 sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc,
                     sht_precision prec, void* hip_stream);
 
@@ -185,7 +190,9 @@ sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, 
  * replays on one plan must not overlap in time (they share the plan's
  * workspace).  Kernel timing is not recorded inside graphs.  The graph
  * refers to the plan: destroy every graph before its plan.  The captured
- * work allocates nothing and contains no memset nodes.
+ * work allocates nothing and contains no memset nodes.  sht_graph_destroy
+ * waits for the graph's last replay (an event recorded by sht_graph_launch),
+ * not for other work on the device, then frees the graph.
  * Errors: SHT_ERR_INVALID_ARG (NULL plan/graph/arrays/buffers, nops outside
  * [1, 64], unknown op, an input equal to its output), SHT_ERR_HIP (capture
  * or instantiation failed). */

@@ -40,14 +40,16 @@ sht_status hip_fail(hipError_t e, const char* what) {
   return fail(SHT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Test hook: SHT_TEST_FAIL_ALLOC=n makes the n-th device allocation of the
-// process fail with hipErrorOutOfMemory (n >= 1).
-int g_alloc_count = 0;
+// Test hook: with SHT_TEST_FAIL_ALLOC=n (n >= 1) in the environment, the
+// n-th device allocation of each sht_plan or sht_plan_tune call fails with
+// hipErrorOutOfMemory.  The count is per thread and restarts at every such
+// call, so plan builds on different threads do not share it.
+thread_local int t_alloc_count = 0;
 
 hipError_t dev_alloc(void** p, size_t bytes) {
-  ++g_alloc_count;
+  ++t_alloc_count;
   const char* env = std::getenv("SHT_TEST_FAIL_ALLOC");
-  if (env && std::atoi(env) == g_alloc_count) {
+  if (env && std::atoi(env) == t_alloc_count) {
     *p = nullptr;
     return hipErrorOutOfMemory;
   }
@@ -152,6 +154,7 @@ struct sht_plan_s {
 
 struct sht_graph_s {
   sht_plan_s* plan = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every replay
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -493,6 +496,7 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
     if (s != SHT_OK) return s;
   }
   // --- first HIP call below this line ---
+  t_alloc_count = 0;
   auto* p = new (std::nothrow) sht_plan_s();
   if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
   p->prec = prec;
@@ -636,6 +640,7 @@ sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const 
   if (!g) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
   g->plan = plan;
   auto cleanup = [&](sht_status rc) {
+    if (g->done) (void)hipEventDestroy(g->done);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->capture) (void)hipStreamDestroy(g->capture);
@@ -644,6 +649,8 @@ sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const 
   };
   hipError_t e = hipStreamCreateWithFlags(&g->capture, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(hip_fail(e, "capture stream"));
+  e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "graph completion event"));
   // the captured work must not depend on earlier work of the plan's stream
   e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamSynchronize"));
@@ -675,16 +682,21 @@ sht_status sht_graph_create(sht_plan_t plan, int nops, const sht_op* ops, const 
 
 sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream) {
   if (!graph) return fail(SHT_ERR_INVALID_ARG, "graph is NULL");
-  hipError_t e = hipGraphLaunch(graph->exec, pick_stream(graph->plan, hip_stream));
+  hipStream_t st = pick_stream(graph->plan, hip_stream);
+  hipError_t e = hipGraphLaunch(graph->exec, st);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  e = hipEventRecord(graph->done, st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   return SHT_OK;
 }
 
 sht_status sht_graph_destroy(sht_graph_t graph) {
   if (!graph) return SHT_OK;
   sht_status rc = SHT_OK;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+  // wait for the last replay only (an event never recorded is complete)
+  hipError_t e = hipEventSynchronize(graph->done);
+  if (e != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+  (void)hipEventDestroy(graph->done);
   if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
   if (graph->graph) (void)hipGraphDestroy(graph->graph);
   if (graph->capture) (void)hipStreamDestroy(graph->capture);
@@ -734,6 +746,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
     }
   }
   // buffers: inputs u (grid), a (spectrum); outputs and the default's copies
+  t_alloc_count = 0;
   const size_t ng = plan->grid_elems, ns = 2 * plan->spec_elems;  // floats
   float* buf[10] = {};
   const size_t sizes[10] = {ng, ns, ns, ng, ns, ng, ns, ng, ns, ng};

@@ -4,15 +4,20 @@
 //
 // Precision forms.  The table is stored as NP bf16 planes (rounded to
 // nearest even from the float64 recurrence: hi = bf16(v), then the
-// residuals); the data (folded DFT output, or spectrum) are split the same
-// way in float32 when they arrive.  With a = sum_i a_i, b = sum_j b_j the
-// kernels form
-//   NP = 1: a_0 b_0                                   (plain bf16)
-//   NP = 2: a_0 b_0 + a_0 b_1 + a_1 b_0               (split bf16)
-//   NP = 3: all a_i b_j with i + j < 3 (six products) (three-term split)
-// i.e. every product whose magnitude is above the representation error of
-// the split.  The correction products of the analysis go into their own
-// accumulator, added to the leading one at the end of each output block.
+// residuals); the data (folded DFT output, or spectrum) are split into ND
+// planes in float32 in VGPRs when they arrive, ND = 1 for plain bf16 and 3
+// otherwise (a third data plane costs no memory traffic).  With
+// a = sum_i a_i (table), b = sum_j b_j (data) the kernels form every
+// product a_i b_j with i < NP, j < ND and i + j < ND:
+//   NP = 1: a_0 b_0                                        (plain bf16)
+//   NP = 2: a_0 b_0 + a_0 b_1 + a_1 b_0 + a_0 b_2 + a_1 b_1 (split bf16)
+//   NP = 3: all a_i b_j with i + j < 3 (six products)      (three-term split)
+// For NP = 2 the only error term left above float32 rounding is the
+// representation error of the two-plane table (at most 2^-16 relative,
+// about 2^-18 on average), so the data's own split and the dropped a_1 b_1
+// product no longer add to it.  The correction products of the analysis go
+// into their own accumulator, added to the leading one at the end of each
+// output block.
 //
 // Structure as in the float32 kernels: one workgroup of four waves per
 // (segment, m, chunk of two field groups), wave (p, j) owns parity p and one
@@ -39,7 +44,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// Split 8 float32 values into NP bf16 planes (residuals in float32).
+// Split 8 float32 values into NP bf16 planes (residuals in float32, exact).
 template <int NP>
 __device__ __forceinline__ void split8(const float* v, bf16x8* out) {
   u16x8 bits[NP];
@@ -57,18 +62,22 @@ __device__ __forceinline__ void split8(const float* v, bf16x8* out) {
   for (int pl = 0; pl < NP; ++pl) out[pl] = __builtin_bit_cast(bf16x8, bits[pl]);
 }
 
-// Products of order below NP between split operands a and b.
-template <int NP>
+// Data planes of the form with NP table planes.
+constexpr int data_planes(int np) { return np == 1 ? 1 : 3; }
+
+// Products a_i b_j (i < NP, j < ND, i + j < ND) between the split table a
+// and the split data b.
+template <int NP, int ND>
 __device__ __forceinline__ void products(const bf16x8* a, const bf16x8* b, floatx4& main, floatx4& corr) {
   main = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], main, 0, 0, 0);
-  if constexpr (NP >= 2) {
+  if constexpr (ND >= 2) {
     corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], corr, 0, 0, 0);
-    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], corr, 0, 0, 0);
+    if constexpr (NP >= 2) corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], corr, 0, 0, 0);
   }
-  if constexpr (NP >= 3) {
+  if constexpr (ND >= 3) {
     corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], corr, 0, 0, 0);
-    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], corr, 0, 0, 0);
-    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], corr, 0, 0, 0);
+    if constexpr (NP >= 2) corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], corr, 0, 0, 0);
+    if constexpr (NP >= 3) corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], corr, 0, 0, 0);
   }
 }
 
@@ -184,7 +193,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   const int f = 8 * cb + (li >> 1);
   const bool fok = active && f < g.F;
   if (nb > 0) {
-    bf16x8 xs[T8][NP];
+    constexpr int ND = data_planes(NP);
+    bf16x8 xs[T8][ND];
     auto issue = [&](auto g_c, int tab_st) {
       constexpr int gs = decltype(g_c)::value;
       v4f* B = rbuf<gs, NBUF>(ring);
@@ -210,8 +220,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
       float v[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = xb[16 * r];
-      split8<NP>(v, xs[2 * u]);
-      split8<NP>(v + 8, xs[2 * u + 1]);
+      split8<ND>(v, xs[2 * u]);
+      split8<ND>(v + 8, xs[2 * u + 1]);
       return true;
     });
     floatx4 main = {0.f, 0.f, 0.f, 0.f}, corr = main;
@@ -232,7 +242,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
             bf16x8 av[NP];
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) av[pl] = as_bf16x8(cur[(p * SC + s * NP + pl) * 64 + lane]);
-            products<NP>(av, xs[part * SS + s], main, corr);
+            products<NP, ND>(av, xs[part * SS + s], main, corr);
           }
           if constexpr (part == PARTS - 1) {
             if (fok) {
@@ -328,7 +338,8 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
       if constexpr ((((i - D) % PARTS) + PARTS) % PARTS == 1) spec_copy(0);
       return true;
     });
-    bf16x8 bv[NP];
+    constexpr int ND = data_planes(NP);
+    bf16x8 bv[ND];
     for (int st0 = 0; st0 < nst; st0 += G::NST) {
       unrolled<0, G::NST>([&](auto su_c) {
         constexpr int su = decltype(su_c)::value;
@@ -342,7 +353,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
           float bn[NB];
 #pragma unroll
           for (int e = 0; e < NB; ++e) bn[e] = wspec[64 * e + lane];
-          split8<NP>(bn, bv);
+          split8<ND>(bn, bv);
         }
         issue_stage<SC, LPW, PARTS>(rbuf<su + D, NBUF>(ring), tab, nb32, nb32, KR * NP, st + D, wave, lane);
         if constexpr (part == 1) spec_copy(ib + 1);
@@ -353,7 +364,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
             bf16x8 av[NP];
 #pragma unroll
             for (int pl = 0; pl < NP; ++pl) av[pl] = as_bf16x8(cur[(p * SC + s * NP + pl) * 64 + lane]);
-            products<NP>(av, bv, acc[part * SS + s], acc[part * SS + s]);
+            products<NP, ND>(av, bv, acc[part * SS + s], acc[part * SS + s]);
           }
         }
         return true;
@@ -371,8 +382,8 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
 
 // LDS ring depth and waves per SIMD: five 16 KiB buffers (four stages in
 // flight) take half of the CU's 160 KiB, so two workgroups share a CU and
-// each wave may use 256 VGPRs (the split forms keep NP planes of the data in
-// VGPRs, up to 144 of them at 384 rings).
+// each wave may use 256 VGPRs (the split forms keep three planes of the data
+// in VGPRs, 144 of them at 384 rings).
 constexpr int kRingBuffers = 5;
 // Synthesis: four buffers plus the 8 KiB spectrum slot.
 constexpr int kSynBuffers = 4;
