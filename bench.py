@@ -7,13 +7,20 @@ equiangular 721 x 1440 grid (both poles, Clenshaw-Curtis weights),
 lmax = mmax = 720.  Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line.  Besides the driver's contract fields it carries:
-  roofline     -- the dominant kernel (Legendre contraction), algorithmic
-                  flops per launch / its average launch time from HIP events
-                  recorded on the launch stream during the timed region;
-  cpu_baseline -- the FP64 NumPy oracle doing the same four transforms on the
-                  host (rank 0, N = 1), with its thread count;
-  err_vs_fp64  -- relative L2 of the SHT output against the oracle on the
-                  same float32 input.
+  roofline       -- the dominant kernel (Legendre contraction): FP32 against
+                    the matrix-core peak with its algorithmic flops, the bf16
+                    forms against HBM with their algorithmic bytes (folded
+                    table in storage form + dense spectrum), per launch, over
+                    its average launch time from HIP events recorded on the
+                    launch stream during the timed region; step_frac is the
+                    whole step against four such launches at that bound;
+  cpu_baseline   -- the FP64 NumPy oracle doing the same four transforms on
+                    the host (rank 0, N = 1): median of three passes after a
+                    warm-up, the oracle's own Legendre recurrence timed apart;
+  err_vs_fp64    -- relative L2 of each of the four GPU stages against the
+                    oracle applied to that stage's own input;
+  step_ms        -- p10 / p50 / p90 of the per-step HIP-event times;
+  graph_replay_ms-- the same four transforms captured as one HIP graph.
 """
 import argparse
 import json
@@ -54,6 +61,22 @@ def legendre_flops(nlat, lmax, mmax, fields):
     nk = (nlat + 1) // 2
     pairs = sum(lmax - m for m in range(mmax))
     return 2.0 * pairs * nk * 2 * fields
+
+
+# matrix-core products per multiply-add of each form (split forms: the
+# products a_i b_j the kernels form)
+PRODUCTS = {"fp32": 1, "bf16": 1, "bf16x2": 5, "bf16x3": 6}
+TABLE_BYTES = {"fp32": 4, "bf16": 2, "bf16x2": 4, "bf16x3": 6}
+
+
+def legendre_bytes(nlat, lmax, mmax, fields, precision):
+    """Algorithmic HBM bytes of one folded Legendre contraction launch: the
+    table of every (l, m) pair at the nk northern rings once, in its storage
+    form, plus the dense complex64 spectrum [fields][lmax][mmax] once.  The
+    DFT intermediate is an implementation cost and is not counted."""
+    nk = (nlat + 1) // 2
+    pairs = sum(lmax - m for m in range(mmax))
+    return pairs * nk * TABLE_BYTES[precision] + fields * lmax * mmax * 8
 
 
 def profiled_traffic(kind, precision):
@@ -277,6 +300,7 @@ def main():
     probe = torch.from_numpy(synth.white_noise(1, (B, C, nlat, nlon)).astype(np.float32)).cuda()
     u = plan.isht(a)
     u.add_(probe)
+    del a, probe
     y = torch.empty(plan.spec_shape(), dtype=torch.complex64, device="cuda")
     x2 = torch.empty(plan.grid_shape(), dtype=torch.float32, device="cuda")
     gy = torch.empty_like(y)
@@ -292,35 +316,68 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # timed region: K eager steps, a HIP event pair around each (on the launch
+    # stream) and around the whole region, plus per-kernel events inside
     plan.set_timing(True)
     plan.read_timing()
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.set_timing(False)
     kernels = plan.read_timing()
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     ms_per_step = wall * 1e3 / args.steps
     value = F * args.steps / wall
 
-    # roofline of the dominant kernel
+    # the same four transforms captured as one HIP graph and replayed (outside
+    # the timed region above; reported beside it)
+    graph = plan.graph([("sht", u, y), ("isht", y, x2), ("isht_T", x2, gy), ("sht_T", gy, gx)])
+    for _ in range(3):
+        graph.launch()
+    torch.cuda.synchronize()
+    gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    gev[0].record(stream)
+    for i in range(args.steps):
+        graph.launch()
+        gev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    graph_ms = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps)])
+    graph.close()
+
+    # roofline of the dominant kernel.  FP32: matrix-core bound, algorithmic
+    # flops of the folded contraction.  bf16 forms: HBM bound, algorithmic
+    # bytes = the folded table in its storage form + the dense spectrum.
     ana_ms, ana_n = kernels["legendre_analysis"]
     syn_ms, syn_n = kernels["legendre_synthesis"]
     kind, tot, n = ("legendre_analysis", ana_ms, ana_n) if ana_ms >= syn_ms else ("legendre_synthesis", syn_ms, syn_n)
     flops = legendre_flops(nlat, L, M, F)
+    nbytes = legendre_bytes(nlat, L, M, F, args.precision)
     avg_s = tot / max(n, 1) * 1e-3
-    peak = PEAKS_TFLOPS[args.precision]
-    achieved = flops / avg_s / 1e12
-    roofline = {"bound": "mfma", "kernel": kind, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_flops_per_launch": flops}
+    if args.precision == "fp32":
+        achieved, peak = flops / avg_s / 1e12, PEAKS_TFLOPS["fp32"]
+        roofline = {"bound": "mfma", "kernel": kind, "achieved": round(achieved, 2), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_flops_per_launch": flops}
+        step_bound_ms = 4 * flops / (peak * 1e12) * 1e3
+    else:
+        achieved, peak = nbytes / avg_s / 1e9, HBM_PEAK_GBS
+        roofline = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": peak,
+                    "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": nbytes,
+                    "mfma_tflops": round(flops * PRODUCTS[args.precision] / avg_s / 1e12, 2)}
+        step_bound_ms = 4 * nbytes / (peak * 1e9) * 1e3
+    p50 = float(np.percentile(step_ms, 50))
+    # the whole step against the sum of its dominant-kernel bounds (four
+    # Legendre launches; the ring DFTs and everything else count as overhead)
+    roofline["step_frac"] = round(step_bound_ms / p50, 4)
     prof = profiled_traffic(kind, args.precision)
     if prof is not None:
         roofline["traffic"] = prof["hbm_bytes_per_launch"]
@@ -328,37 +385,53 @@ def main():
         roofline["traffic_source"] = prof["source"]
     per_kernel_us = {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in kernels.items() if v[1]}
 
-    # accuracy of this run's SHT against the FP64 oracle; CPU baseline timing
+    # CPU baseline: the FP64 oracle doing the same four transforms on the host
+    # (each stage fed the GPU stage's input, so the same pass also gives every
+    # stage's error); one untimed warm-up pass, then the median of three.  The
+    # oracle rebuilds each order's Legendre rows inside every transform; that
+    # recurrence is timed on its own and reported separately.
     err = None
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
+        from oracle.legendre import iter_orders
         try:
             from threadpoolctl import threadpool_info
             blas_threads = max([i.get("num_threads", 0) for i in threadpool_info()] or [0])
         except Exception:
             blas_threads = 0
         nf = max(1, min(args.cpu_fields, F))
-        u_host = u.cpu().numpy().astype(np.float64)[:, :nf]
-        # repeat the pass until about 10 s of CPU work (at most 4 passes)
+        ins = [t.cpu().numpy()[:, :nf] for t in (u, y, x2, gy)]
+        outs = [t.cpu().numpy()[:, :nf] for t in (y, x2, gy, gx)]
+        u_h, y_h, x_h, gy_h = ins[0].astype(np.float64), ins[1].astype(np.complex128), \
+            ins[2].astype(np.float64), ins[3].astype(np.complex128)
+
+        def cpu_pass():
+            return (oracle.sht(u_h, L, M, 0), oracle.isht(y_h, nlat, nlon, 0),
+                    oracle.isht_T(x_h, L, M, 0), oracle.sht_T(gy_h, nlat, nlon, 0))
+
+        refs = cpu_pass()                      # warm-up
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            cpu_pass()
+            times.append(time.perf_counter() - t0)
+        th, xk, _ = oracle.grid(nlat, 0)
         t0 = time.perf_counter()
-        reps = 0
-        while True:
-            ry = oracle.sht(u_host, L, M, 0)
-            rx = oracle.isht(ry, nlat, nlon, 0)
-            rgy = oracle.isht_T(rx, L, M, 0)
-            oracle.sht_T(rgy, nlat, nlon, 0)
-            reps += 1
-            cpu_s = time.perf_counter() - t0
-            if cpu_s >= 10.0 or reps >= 4:
-                break
-        yg = y.cpu().numpy()[:, :nf]
-        err = float(np.linalg.norm((yg - ry).ravel()) / np.linalg.norm(ry.ravel()))
-        cpu = {"value": round(nf * reps / cpu_s, 3), "unit": "fields/s", "cores": blas_threads or os.cpu_count(),
-               "kind": "oracle",
-               "sample": f"{nf} of the {F} fields, full 721x1440 grid, {reps} SHT->ISHT->ISHT^T->SHT^T pass(es) in "
-                         f"float64 ({cpu_s:.1f} s); os.cpu_count()={os.cpu_count()}, "
-                         f"affinity={len(os.sched_getaffinity(0))}"}
+        for _m, _rows in iter_orders(L, M, xk, np.sin(th)):
+            pass
+        table_s = time.perf_counter() - t0
+        med = float(np.median(times))
+        err = {name: float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+               for name, got, ref in zip(("sht", "isht", "isht_T", "sht_T"), outs, refs)}
+        cpu = {"value": round(nf / max(med - 4 * table_s, 1e-9), 3), "unit": "fields/s",
+               "cores": blas_threads or os.cpu_count(), "kind": "oracle",
+               "value_incl_table": round(nf / med, 3),
+               "sample": f"{nf} of the {F} fields, full 721x1440 grid: SHT, ISHT, ISHT^T, SHT^T in float64; median "
+                         f"of 3 passes after 1 warm-up ({med:.2f} s per pass), minus the oracle's own Legendre "
+                         f"recurrence (4 x {table_s:.2f} s per pass, reported as table_build_s); "
+                         f"os.cpu_count()={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}",
+               "table_build_s": round(table_s, 3)}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
@@ -370,8 +443,13 @@ def main():
                    "nlat": nlat, "nlon": nlon, "lmax": L, "mmax": M, "fields": F, "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "err_vs_fp64": {"sht_rel_l2": err},
+        "err_vs_fp64": err,
         "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
+        "step_ms": {"p10": round(float(np.percentile(step_ms, 10)), 4), "p50": round(p50, 4),
+                    "p90": round(float(np.percentile(step_ms, 90)), 4)},
+        "graph_replay_ms": {"p10": round(float(np.percentile(graph_ms, 10)), 4),
+                            "p50": round(float(np.percentile(graph_ms, 50)), 4),
+                            "p90": round(float(np.percentile(graph_ms, 90)), 4)},
         "kernel_avg_us": per_kernel_us,
         "plan_build_s": round(plan_s, 3),
     }
