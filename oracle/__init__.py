@@ -36,7 +36,7 @@ from .grids import (equiangular_nodes, gauss_legendre, clenshaw_curtis_weights,
                     trapezoid_weights, grid)
 from .legendre import legendre_order, legendre_table
 from .transforms import sht, isht, sht_T, isht_T, sht_bruteforce, isht_bruteforce
-from .mix import channel_mix, channel_mix_T, channel_mix_dW
+from .mix import channel_mix, channel_mix_T, channel_mix_dW, isotropic_filter, isotropic_filter_T, isotropic_filter_dk
 from .scores import (crps_integral, crps_sorted, crps_spread_skill, spectral_crps, spatial_crps,
                      psd, zonal_psd, crps_spread_skill_grad, spectral_crps_grad, spatial_crps_grad)
 from .noise import philox4x64_10, normal_pairs, diffusion_params, diffusion_step
@@ -45,7 +45,7 @@ __all__ = [
     "equiangular_nodes", "gauss_legendre", "clenshaw_curtis_weights",
     "trapezoid_weights", "grid", "legendre_order", "legendre_table",
     "sht", "isht", "sht_T", "isht_T", "sht_bruteforce", "isht_bruteforce",
-    "channel_mix", "channel_mix_T", "channel_mix_dW",
+    "channel_mix", "channel_mix_T", "channel_mix_dW", "isotropic_filter", "isotropic_filter_T", "isotropic_filter_dk",
     "crps_integral", "crps_sorted", "crps_spread_skill", "spectral_crps", "spatial_crps", "psd", "zonal_psd",
     "crps_spread_skill_grad", "spectral_crps_grad", "spatial_crps_grad",
     "philox4x64_10", "normal_pairs", "diffusion_params", "diffusion_step",

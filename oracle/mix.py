@@ -8,6 +8,9 @@ weight for every order m, here a complex C x C matrix W_l:
 
 Adjoint under the real inner product Re sum conj(a) b:
     g_x[b, c, l, m] = sum_c' conj(W[l, c', c]) g_y[b, c', l, m]
+
+The single-channel form of the same theorem, one isotropic filter k[c, l]
+per channel ((u * k)^_l^m = u^_l^m k^_l^0), is ``isotropic_filter``.
 """
 import numpy as np
 
@@ -55,3 +58,29 @@ def channel_mix_dW(g, x, degrees=None):
         xl = np.transpose(x[:, :, l, :mc], (1, 0, 2)).reshape(C, B * mc)
         dW[i] = gl @ np.conj(xl).T
     return dW
+
+
+def isotropic_filter(x, k):
+    """The spectral convolution of eq. s2_spectral_conv with one isotropic
+    filter per channel: y[b, c, l, m] = k[c, l] x[b, c, l, m] (the filter
+    depends on the degree only).  x complex [B, C, lmax, mmax], k complex
+    [C, lmax]."""
+    x = np.asarray(x, dtype=np.complex128)
+    k = np.asarray(k, dtype=np.complex128)
+    return k[None, :, :, None] * x
+
+
+def isotropic_filter_T(g, k):
+    """Adjoint of ``isotropic_filter`` with respect to x: conj(k) g."""
+    return isotropic_filter(g, np.conj(np.asarray(k, dtype=np.complex128)))
+
+
+def isotropic_filter_dk(g, x):
+    """Gradient of a real loss with respect to the filter of
+    ``isotropic_filter`` (PyTorch's complex convention):
+    dk[c, l] = sum_b sum_{m <= min(l, mmax - 1)} g[b, c, l, m] conj(x[b, c, l, m])."""
+    g = np.asarray(g, dtype=np.complex128)
+    x = np.asarray(x, dtype=np.complex128)
+    lmax, mmax = x.shape[-2], x.shape[-1]
+    mask = (np.arange(mmax)[None, :] <= np.arange(lmax)[:, None])
+    return np.sum(g * np.conj(x) * mask, axis=(0, 3))
