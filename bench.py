@@ -47,10 +47,15 @@ def parse():
                     help="only copy a 256 MiB device buffer three times (reference kernel for HBM counters)")
     ap.add_argument("--cpu-fields", type=int, default=72,
                     help="fields in the oracle's timed sample (of the 72)")
-    ap.add_argument("--workload", default="sht721", choices=["sht721", "batched", "sfno_block"],
+    ap.add_argument("--workload", default="sht721", choices=["sht721", "batched", "sfno_block", "scores", "noise"],
                     help="sht721: the headline single-grid step; batched: uneven grids in one plan, "
                          "graph-replayed, with p50/p99 replay latency")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batched workload)")
+    ap.add_argument("--schedule", default=None,
+                    help="chunk,policy,ncb: an explicit work schedule for the Legendre kernels (results unchanged)")
+    ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing (sht721)")
+    ap.add_argument("--block-batch", type=int, default=4, help="sfno_block: batch (ensemble members)")
+    ap.add_argument("--block-channels", type=int, default=256, help="sfno_block: channels (677 in the model)")
     return ap.parse_args()
 
 
@@ -195,13 +200,16 @@ def sfno_block_bench(args):
     with the weight gradient: SHT, mix, ISHT, then ISHT^T, mix^T, dW, SHT^T
     (FP32).  Per-kernel times from HIP events on the launch stream; the
     roofline of the channel-mix kernels (mix, mix^T and dW: per launch
-    8 C^2 sum_l B min(l + 1, mmax) flops) is against the FP32 vector peak."""
+    8 C^2 sum_l B min(l + 1, mmax) flops) is against the FP32 matrix-core
+    peak (the kernels run on v_mfma_f32_16x16x4_f32)."""
     import numpy as np
     import torch
     import paper_2507_12144_amd as P
     torch.cuda.set_device(0)
-    nlat, nlon, L, B, C = 360, 720, 360, 4, 256
+    nlat, nlon, L, B, C = 360, 720, 360, args.block_batch, args.block_channels
     plan = P.Plan(dict(nlat=nlat, nlon=nlon, lmax=L, mmax=L, grid="gauss", batch=B, channels=C))
+    if args.schedule:
+        plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
     gen = torch.Generator(device="cuda")
     gen.manual_seed(0)
     x = torch.randn(plan.grid_shape(), device="cuda", generator=gen)
@@ -250,10 +258,10 @@ def sfno_block_bench(args):
         "value": round(F * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "Gauss 360x720, lmax=mmax=360, batch 4 x 256 channels; SHT -> mix_W -> ISHT "
+        "config": {"workload": f"Gauss 360x720, lmax=mmax=360, batch {B} x {C} channels; SHT -> mix_W -> ISHT "
                                "then ISHT^T -> mix_W^H and dW -> SHT^T",
                    "nlat": nlat, "nlon": nlon, "lmax": L, "mmax": L, "fields": F, "channels": C},
-        "roofline": {"bound": "alu", "kernel": "channel_mix (mix, mix^H, dW)", "achieved": round(achieved, 2),
+        "roofline": {"bound": "mfma", "kernel": "channel_mix (mix, mix^H, dW)", "achieved": round(achieved, 2),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                      "avg_launch_us": round(mix_us, 2), "algorithmic_flops_per_launch": mix_flops},
         "cpu_baseline": None,
@@ -264,16 +272,143 @@ def sfno_block_bench(args):
     plan.close()
 
 
+def scores_bench(args):
+    """The consumers of the 721 x 1440 spectra: per step, for an ensemble of
+    16 members x 8 channels, the spectral CRPS loss with its gradient
+    (l <= 360, the paper's range), the angular PSD and the zonal PSD of every
+    ring.  Roofline of the CRPS kernel against HBM: algorithmic bytes = the
+    live coefficients (1 <= l <= 360, m <= l) of the ensemble and the
+    observation read once, the full gradient tensor written once."""
+    import numpy as np
+    import torch
+    import paper_2507_12144_amd as P
+    torch.cuda.set_device(0)
+    nlat, nlon, L, N, C = 721, 1440, 720, 16, 8
+    plan = P.Plan(dict(nlat=nlat, nlon=nlon, lmax=L, mmax=L, grid="equiangular", batch=N, channels=C))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    u = torch.randn(plan.grid_shape(), device="cuda", generator=gen)
+    ens = plan.sht(u)
+    obs = ens[0].clone()
+    ens = ens + 0.1 * torch.randn(ens.shape, dtype=torch.complex64, device="cuda", generator=gen)
+    g = torch.empty_like(ens)
+    loss = torch.empty(C, device="cuda")
+    psd = torch.empty((N, C, L), device="cuda")
+    zpsd = torch.empty((N, C, nlat, L), device="cuda")
+    lib = P._lib.load()
+    import ctypes
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def step():
+        P._lib.check(lib.sht_spectral_crps(plan._h, ctypes.c_void_p(ens.data_ptr()), ctypes.c_void_p(obs.data_ptr()),
+                                           0, 0, ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(g.data_ptr()), st))
+        plan.psd(ens, out=psd)
+        plan.zonal_psd(u, out=zpsd)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.read_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_timing(False)
+    kt = plan.read_timing()
+    # per-kernel times from a separate timed pass of each (kind 6 covers all three)
+    times = {}
+    for name, fn in (("spectral_crps", lambda: P._lib.check(lib.sht_spectral_crps(
+            plan._h, ctypes.c_void_p(ens.data_ptr()), ctypes.c_void_p(obs.data_ptr()), 0, 0,
+            ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(g.data_ptr()), st))),
+                     ("psd", lambda: plan.psd(ens, out=psd)), ("zonal_psd", lambda: plan.zonal_psd(u, out=zpsd))):
+        plan.set_timing(True)
+        plan.read_timing()
+        for _ in range(args.steps):
+            fn()
+        ms, n = plan.read_timing()["scores"]
+        plan.set_timing(False)
+        times[name] = 1000.0 * ms / n
+    lhi = min(L - 1, nlat // 2)
+    live = sum(min(l, L - 1) + 1 for l in range(1, lhi + 1))
+    nbytes = (N + 1) * C * live * 8 + N * C * L * L * 8
+    crps_us = times["spectral_crps"]
+    achieved = nbytes / (crps_us * 1e-6) / 1e9
+    out = {
+        "metric": "spectral CRPS loss+gradient, angular PSD and zonal PSD fields/sec at 721x1440 lmax720",
+        "value": round(N * C * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 members x 8 channels, equiangular 721x1440, lmax=mmax=720: spectral CRPS "
+                               "(l <= 360) with gradient, angular PSD, zonal PSD of every ring",
+                   "members": N, "channels": C},
+        "roofline": {"bound": "hbm", "kernel": "spectral_crps", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(crps_us, 2), "algorithmic_bytes_per_launch": nbytes},
+        "cpu_baseline": None,
+        "kernel_avg_us": {k: round(v, 2) for k, v in times.items()},
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+def noise_bench(args):
+    """The spherical diffusion noise of the paper's model input: 8 channels
+    with the Table 1 length scales (lambda = 1, sigma = 1) for 16 ensemble
+    members on the 721 x 1440 grid, lmax = mmax = 720; one step = one AR(1)
+    update of every coefficient (Philox4x64-10 + Box-Muller in float64) and
+    the ISHT of the new state."""
+    import torch
+    import paper_2507_12144_amd as P
+    torch.cuda.set_device(0)
+    nlat, nlon, L, B, C = 721, 1440, 720, 16, 8
+    kT = [3.08e-5, 1.23e-4, 4.93e-4, 1.97e-3, 7.89e-3, 3.16e-2, 1.26e-1, 5.05e-1]
+    plan = P.Plan(dict(nlat=nlat, nlon=nlon, lmax=L, mmax=L, grid="equiangular", batch=B, channels=C))
+    noise = P.Noise(plan, kT, [1.0] * C, [1.0] * C, seed=2025)
+    z = torch.empty(plan.grid_shape(), device="cuda")
+    for _ in range(args.warmup):
+        noise.step(out=z)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.read_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        noise.step(out=z)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = plan.read_timing()
+    plan.set_timing(False)
+    avg = {k: round(1000.0 * v[0] / v[1], 2) for k, v in kt.items() if v[1]}
+    coeffs = B * C * L * L
+    out = {
+        "metric": "spherical diffusion noise fields/sec (AR(1) spectral step + ISHT) at 721x1440 lmax720",
+        "value": round(B * C * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16 members x 8 Table-1 noise channels, equiangular 721x1440, lmax=mmax=720",
+                   "members": B, "channels": C},
+        "noise_step": {"avg_launch_us": avg.get("noise"), "coefficients": coeffs,
+                       "gcoeff_per_s": round(coeffs / (avg.get("noise", float("nan")) * 1e-6) / 1e9, 2)},
+        "cpu_baseline": None,
+        "kernel_avg_us": avg,
+    }
+    print(json.dumps(out), flush=True)
+    noise.close()
+    plan.close()
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload in ("batched", "sfno_block"):
+    if args.workload in ("batched", "sfno_block", "scores", "noise"):
         if args.gpus != 1:
             print("bench.py: this build measures one GPU only", file=sys.stderr, flush=True)
             sys.exit(2)
-        (batched_bench if args.workload == "batched" else sfno_block_bench)(args)
+        {"batched": batched_bench, "sfno_block": sfno_block_bench, "scores": scores_bench,
+         "noise": noise_bench}[args.workload](args)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
@@ -294,6 +429,12 @@ def main():
                   precision=args.precision)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
+    tuned = None
+    if args.schedule:
+        plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    elif args.tune:
+        choice, tune_ms = plan.tune(args.tune_cache)
+        tuned = {"candidate": choice, "best_pass_ms": round(tune_ms, 3)}
 
     # synthetic input: band-limited field (seed 0) + 1e-3 white-noise probe (seed 1)
     a = torch.from_numpy(synth.coefficients(0, B, C, L, M).astype(np.complex64)).cuda()

@@ -108,7 +108,8 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc,
 
 /* Synchronise the plan's stream and free everything the plan owns.
  * NULL is accepted and ignored.  SHT_ERR_INVALID_ARG (nothing freed) while
- * graphs of the plan (sht_graph_create) still exist. */
+ * graphs (sht_graph_create) or noise generators (sht_noise_create) of the
+ * plan still exist. */
 sht_status sht_plan_destroy(sht_plan_t plan);
 
 /* Element offsets of segment i inside the concatenated grid buffer (float32
@@ -168,14 +169,101 @@ sht_status sht_channel_mix(sht_plan_t plan, const void* W, const void* in, void*
 sht_status sht_channel_mix_weight_grad(sht_plan_t plan, const void* g, const void* x, void* dW,
                                        void* hip_stream);
 
+/* Angular power spectral density (App. F.7, eq. psd) of a spectrum of a
+ * single-segment plan: out[b][c][l] = sum over |m| <= l of |y_l^m|^2 =
+ * sum_{m <= min(l, mmax-1)} c_m |y[b][c][l][m]|^2 with c_0 = 1, c_m = 2 (real
+ * fields, u^_l^{-m} = (-1)^m conj(u^_l^m)).  y: spectral tensor (device,
+ * read); out: float32 [batch][channels][lmax] (device, written).  Timed as
+ * kind 6 (scores). */
+sht_status sht_psd(sht_plan_t plan, const void* y, float* out, void* hip_stream);
+
+/* Zonal power spectral density (App. F.7, eq. zonal_psd) at every ring of a
+ * single-segment plan's grid tensor:
+ *   out[b][c][k][m] = 2 pi sin(t_k) |(2 pi/nlon) sum_j x[b][c][k][j] e^{-2 pi i j m/nlon}|^2,
+ * m < mmax.  x: grid tensor (device, read); out: float32
+ * [batch][channels][nlat][mmax] (device, written; must not alias x).  One
+ * launch of the ring DFT with a zonal epilogue.  Timed as kind 6. */
+sht_status sht_zonal_psd(sht_plan_t plan, const float* x, float* out, void* hip_stream);
+
+/* Spectral CRPS loss term (App. E.1, eq. spectral_loss) of an ensemble
+ * against an observation, single-segment plan whose batch is the ensemble
+ * (N = batch members, 1 <= N <= 64; N >= 2 for the fair form):
+ *   loss[c] = sum_{1 <= l <= l_hi} sum_{m <= l} c_m (CRPS(Re) + CRPS(Im))
+ * with CRPS over the N members in the spread-skill form (App. D.4, eq.
+ * spread_skill_crps; fair != 0: eq. fair_spread_skill_crps), c_0 = 1,
+ * c_m = 2 (the orders -m of real fields), real and imaginary parts as two
+ * real marginals.  l_hi <= 0 selects min(lmax - 1, nlat / 2), the paper's
+ * range.  ens: spectral tensor of the plan [N][C][lmax][mmax] (device);
+ * obs: complex64 [C][lmax][mmax] (device); loss: float32 [C] (device,
+ * written); grad: NULL, or complex64 like ens (device, written in full)
+ * receiving d(sum_c loss[c])/dRe + i d/dIm with |.|' = sign(.), sign(0) = 0
+ * (PyTorch's complex convention, ready for sht_backward).  Row sums go
+ * through plan-owned scratch: calls on one plan must not overlap.  Results
+ * are bitwise reproducible (fixed summation order).  Timed as kind 6. */
+sht_status sht_spectral_crps(sht_plan_t plan, const void* ens, const void* obs, int fair, int l_hi, float* loss,
+                             void* grad, void* hip_stream);
+
+/* Spatial CRPS loss term (App. E.1, eq. spatial_loss): the point-wise CRPS
+ * of the N = batch members averaged over the sphere,
+ *   loss[c] = (1/4 pi) sum_k sum_j (2 pi/nlon) w_k CRPS_kj,
+ * ens: grid tensor of the plan [N][C][nlat][nlon] (device); obs: float32
+ * [C][nlat][nlon] (device); loss, grad as for sht_spectral_crps (grad:
+ * float32 like ens).  Timed as kind 6. */
+sht_status sht_spatial_crps(sht_plan_t plan, const float* ens, const float* obs, int fair, float* loss, float* grad,
+                            void* hip_stream);
+
+/* Spherical diffusion noise (App. B.7, eq. spherical_diffusion): for every
+ * member b and channel c of a single-segment plan an AR(1) process of
+ * spectral coefficients
+ *   a_n = phi_c a_{n-1} + sigma_{c,l} eta,  phi_c = e^{-lambda_c},
+ *   sigma_{c,l} = F_0 e^{-k_T,c l (l+1) / 2},
+ *   F_0 = sigma_c sqrt(2 pi (1 - phi_c^2) / sum_{0 < l < lmax} (2l+1) e^{-k_T,c l (l+1)}),
+ * with eta standard normal per coefficient (Philox4x64-10 counter (flat
+ * coefficient index, step, 0, 0), key (seed, 0); Box-Muller in float64):
+ * sigma_l (eta_re + i eta_im) for m >= 1, sqrt(2) sigma_l eta_re for m = 0,
+ * degree 0 and l < m zero, so the stationary point-wise variance is
+ * sigma_c^2.  sht_noise_create: kT, lambda, sigma are HOST arrays of
+ * `channels` doubles (k_T > 0, lambda > 0, sigma >= 0); the generator keeps
+ * a step counter starting at 0 and refers to the plan (destroy it first).
+ * sht_noise_step: state is the plan's spectral tensor (device, read and
+ * written in place; ignored at step 0, which draws the stationary start);
+ * with z != NULL the ISHT of the new state is written to z (grid tensor,
+ * device).  Advances the counter.  sht_noise_set_step sets the counter
+ * (restart from a saved state).  Timed as kind 7 (noise). */
+typedef struct sht_noise_s* sht_noise_t;
+sht_status sht_noise_create(sht_plan_t plan, const double* kT, const double* lambda, const double* sigma,
+                            unsigned long long seed, sht_noise_t* out);
+sht_status sht_noise_step(sht_noise_t noise, void* state, float* z, void* hip_stream);
+sht_status sht_noise_set_step(sht_noise_t noise, unsigned long long step);
+sht_status sht_noise_destroy(sht_noise_t noise);
+
+/* Isotropic spectral filter, the spectral convolution of App. B.4 (eq.
+ * s2_spectral_conv: (u * k)^_l^m = u^_l^m k^_l^0) with one filter per
+ * channel, for a plan with one segment:
+ *   out[b,c,l,m] = k[c,l] in[b,c,l,m]   (adjoint != 0: conj(k[c,l])),
+ * entries m > l written as 0.  k: complex64 [channels][lmax] (device);
+ * in/out: spectral tensors of the plan's shape (device, must not alias).
+ * Timed as kind 5. */
+sht_status sht_isotropic_filter(sht_plan_t plan, const void* k, const void* in, void* out, int adjoint,
+                                void* hip_stream);
+
+/* Filter gradient of sht_isotropic_filter: for a real loss of
+ * y = filter(k, x) with g = dL/dRe y + i dL/dIm y,
+ *   dk[c,l] = sum_b sum_{m <= min(l, mmax-1)} g[b,c,l,m] conj(x[b,c,l,m])
+ * (PyTorch's complex convention).  g, x: spectral tensors (device, read);
+ * dk: complex64 [channels][lmax] (device, written in full).  Fixed
+ * summation order.  Timed as kind 5. */
+sht_status sht_isotropic_filter_grad(sht_plan_t plan, const void* g, const void* x, void* dk, void* hip_stream);
+
 /* Kernel timing (diagnostics).  With enable != 0 every later call on the
  * plan records a pair of HIP events on the call's stream around each kernel
  * it launches.  sht_plan_timing_read waits for the recorded events, adds the
  * elapsed milliseconds and launch counts per kernel kind into ms[i] and
  * counts[i] for i < nkinds (kinds: 0 ring DFT forward, 1 ring DFT inverse,
- * 2 Legendre analysis, 3 Legendre synthesis, 4 zero fill, 5 channel mix),
+ * 2 Legendre analysis, 3 Legendre synthesis, 4 zero fill, 5 channel mix,
+ * 6 scores and spectra, 7 noise),
  * then forgets them.  Host arrays; nkinds <= SHT_TIMING_KINDS. */
-#define SHT_TIMING_KINDS 6
+#define SHT_TIMING_KINDS 8
 sht_status sht_plan_timing(sht_plan_t plan, int enable);
 sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds);
 
@@ -204,21 +292,31 @@ sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream);
 sht_status sht_graph_destroy(sht_graph_t graph);
 
 /* Autotuner.  The work decomposition of a plan has free parameters that do
- * not change any result bit: the orders per scheduling chunk of the
- * Legendre work list (4, 8, 16, 32) and how chunks are dealt to the 8
- * XCDs (largest-first to the least-loaded XCD, or round robin).  sht_plan_tune
- * times one SHT -> ISHT -> ISHT^T -> SHT^T pass per candidate (after one
- * warm-up pass) on library-allocated synthetic buffers, requires every
- * candidate's four outputs to equal the default candidate's bit for bit
- * (parity), keeps the fastest, and returns its index in *chosen and its
- * time in *best_ms (either may be NULL).  With cache_path != NULL the
- * choice is looked up first in that text file under a key of (gfx arch,
- * descriptors, precision) and appended to it after a measurement; a cached
- * choice is applied without timing (*best_ms = -1).  Synchronises the
- * plan's stream.  Errors: SHT_ERR_INVALID_ARG (NULL plan),
+ * not change any result bit: the field groups (of 8 fields) per workgroup
+ * of the float32 Legendre kernels (2, 3 or 4; the bf16 forms always take 2),
+ * the orders per scheduling chunk of the Legendre work list (4, 8, 16, 32)
+ * and how chunks are dealt to the 8 XCDs (largest-first to the least-loaded
+ * XCD, or round robin).  sht_plan_tune times one SHT -> ISHT -> ISHT^T ->
+ * SHT^T pass per candidate (after one warm-up pass) on library-allocated
+ * synthetic buffers, requires every candidate's four outputs to equal the
+ * default candidate's bit for bit (parity), keeps the fastest, and returns
+ * its index in *chosen and its time in *best_ms (either may be NULL).  With
+ * cache_path != NULL the choice is looked up first in that text file under a
+ * key of (gfx arch, descriptors, precision, candidate-list version) and
+ * appended to it after a measurement; a cached choice is applied without
+ * timing (*best_ms = -1).  Synchronises the plan's stream.  Errors:
+ * SHT_ERR_INVALID_ARG (NULL plan, graphs of the plan exist),
  * SHT_ERR_OUT_OF_MEMORY, SHT_ERR_HIP, SHT_ERR_INTERNAL (a candidate's
  * outputs differ from the default's). */
 sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, double* best_ms);
+
+/* Set the schedule explicitly (chunk: orders per chunk, 1..64; policy: 0
+ * least-loaded XCD, 1 round robin; ncb: field groups per workgroup of the
+ * float32 kernels, 2..4, ignored by the bf16 forms), or read the one in
+ * use.  Results do not change.  SHT_ERR_INVALID_ARG while graphs of the plan
+ * exist (they hold the old work list). */
+sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb);
+sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb);
 
 const char* sht_status_string(sht_status s);
 const char* sht_last_error(void);

@@ -13,7 +13,8 @@ import torch
 from . import _lib
 from ._lib import GRIDS, PRECISIONS, ShtError
 
-__all__ = ["Plan", "SHT", "ISHT", "ChannelMix", "ShtError", "GRIDS", "PRECISIONS"]
+__all__ = ["Plan", "SHT", "ISHT", "ChannelMix", "IsotropicFilter", "SpectralCRPS", "SpatialCRPS", "Noise", "ShtError", "GRIDS",
+           "PRECISIONS"]
 
 
 def _stream_ptr(device):
@@ -146,6 +147,94 @@ class Plan:
                                                            _stream_ptr(self.device)))
         return out
 
+    def filter(self, k, x, adjoint=False, out=None):
+        """Isotropic filter out[b,c,l,m] = k[c,l] x[b,c,l,m] (adjoint:
+        conj(k)).  k: complex64 [channels, lmax]."""
+        d = self.descs[0]
+        C = d.get("channels", 1)
+        self._check(k, torch.complex64, (C, d["lmax"]), "k")
+        self._check(x, torch.complex64, self.spec_shape(), "input")
+        if out is None:
+            out = torch.empty(self.spec_shape(), dtype=torch.complex64, device=self.device)
+        self._check(out, torch.complex64, self.spec_shape(), "output")
+        _lib.check(_lib.load().sht_isotropic_filter(self._h, ctypes.c_void_p(k.data_ptr()),
+                                                    ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                    1 if adjoint else 0, _stream_ptr(self.device)))
+        return out
+
+    def filter_grad(self, g, x, out=None):
+        """Filter gradient dk[c,l] = sum over b and m <= l of g conj(x)."""
+        d = self.descs[0]
+        C = d.get("channels", 1)
+        self._check(g, torch.complex64, self.spec_shape(), "g")
+        self._check(x, torch.complex64, self.spec_shape(), "x")
+        if out is None:
+            out = torch.empty((C, d["lmax"]), dtype=torch.complex64, device=self.device)
+        self._check(out, torch.complex64, (C, d["lmax"]), "dk")
+        _lib.check(_lib.load().sht_isotropic_filter_grad(self._h, ctypes.c_void_p(g.data_ptr()),
+                                                         ctypes.c_void_p(x.data_ptr()),
+                                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(self.device)))
+        return out
+
+    # ------------------------------------------------- scores and spectra
+    def psd(self, y, out=None):
+        """Angular power spectral density sum_{|m| <= l} |y_l^m|^2:
+        float32 [batch, channels, lmax]."""
+        d = self.descs[0]
+        self._check(y, torch.complex64, self.spec_shape(), "y")
+        shape = (d.get("batch", 1), d.get("channels", 1), d["lmax"])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._check(out, torch.float32, shape, "out")
+        _lib.check(_lib.load().sht_psd(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(self.device)))
+        return out
+
+    def zonal_psd(self, x, out=None):
+        """Zonal power spectral density 2 pi sin(t_k) |(2 pi/nlon) DFT_m|^2 of
+        every ring: float32 [batch, channels, nlat, mmax]."""
+        d = self.descs[0]
+        self._check(x, torch.float32, self.grid_shape(), "x")
+        shape = (d.get("batch", 1), d.get("channels", 1), d["nlat"], d["mmax"])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._check(out, torch.float32, shape, "out")
+        _lib.check(_lib.load().sht_zonal_psd(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             _stream_ptr(self.device)))
+        return out
+
+    def spectral_crps(self, ens, obs, fair=False, l_hi=0, grad=False):
+        """Spectral CRPS loss per channel over the ensemble (the plan's batch):
+        returns loss float32 [channels] (and its gradient with respect to ens,
+        complex64 like ens, when grad=True)."""
+        d = self.descs[0]
+        C = d.get("channels", 1)
+        self._check(ens, torch.complex64, self.spec_shape(), "ens")
+        self._check(obs, torch.complex64, (C, d["lmax"], d["mmax"]), "obs")
+        loss = torch.empty(C, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(ens) if grad else None
+        _lib.check(_lib.load().sht_spectral_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
+                                                 ctypes.c_void_p(obs.data_ptr()), 1 if fair else 0, int(l_hi),
+                                                 ctypes.c_void_p(loss.data_ptr()),
+                                                 ctypes.c_void_p(g.data_ptr() if grad else None),
+                                                 _stream_ptr(self.device)))
+        return (loss, g) if grad else loss
+
+    def spatial_crps(self, ens, obs, fair=False, grad=False):
+        """Spatial CRPS loss per channel (quadrature average over the sphere)."""
+        d = self.descs[0]
+        C = d.get("channels", 1)
+        self._check(ens, torch.float32, self.grid_shape(), "ens")
+        self._check(obs, torch.float32, (C, d["nlat"], d["nlon"]), "obs")
+        loss = torch.empty(C, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(ens) if grad else None
+        _lib.check(_lib.load().sht_spatial_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
+                                                ctypes.c_void_p(obs.data_ptr()), 1 if fair else 0,
+                                                ctypes.c_void_p(loss.data_ptr()),
+                                                ctypes.c_void_p(g.data_ptr() if grad else None),
+                                                _stream_ptr(self.device)))
+        return (loss, g) if grad else loss
+
     # ----------------------------------------------------- batching helpers
     def tune(self, cache=None):
         """Autotune the work schedule (sht_plan_tune); returns (candidate, ms),
@@ -154,6 +243,16 @@ class Plan:
         path = None if cache is None else str(cache).encode()
         _lib.check(_lib.load().sht_plan_tune(self._h, path, ctypes.byref(chosen), ctypes.byref(ms)))
         return chosen.value, ms.value
+
+    def set_schedule(self, chunk=8, policy=0, ncb=2):
+        """Set the work schedule explicitly (results do not change)."""
+        _lib.check(_lib.load().sht_plan_set_schedule(self._h, int(chunk), int(policy), int(ncb)))
+
+    def schedule(self):
+        """(orders per chunk, XCD policy, field groups per workgroup) in use."""
+        c, p, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(_lib.load().sht_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(n)))
+        return c.value, p.value, n.value
 
     def graph(self, ops):
         """Capture a sequence [(op, input, output), ...] (op in "sht", "isht",
@@ -231,6 +330,95 @@ class ChannelMix(torch.autograd.Function):
         gx = ctx.plan.mix(W, g, adjoint=True) if ctx.needs_input_grad[0] else None
         gW = ctx.plan.mix_weight_grad(g, x) if ctx.needs_input_grad[1] else None
         return gx, gW, None
+
+
+class IsotropicFilter(torch.autograd.Function):
+    """y = k_l x per channel and degree; backward gives conj(k) g and, when k
+    requires it, the filter gradient sum_{b, m <= l} g conj(x)."""
+
+    @staticmethod
+    def forward(ctx, x, k, plan):
+        ctx.plan = plan
+        x = x.contiguous()
+        ctx.save_for_backward(k, x)
+        return plan.filter(k, x)
+
+    @staticmethod
+    def backward(ctx, g):
+        k, x = ctx.saved_tensors
+        g = g.contiguous()
+        gx = ctx.plan.filter(k, g, adjoint=True) if ctx.needs_input_grad[0] else None
+        gk = ctx.plan.filter_grad(g, x) if ctx.needs_input_grad[1] else None
+        return gx, gk, None
+
+
+class SpectralCRPS(torch.autograd.Function):
+    """loss[c] = spectral CRPS of the ensemble spectra against the observed
+    spectrum; backward scales the kernel's gradient by the incoming one."""
+
+    @staticmethod
+    def forward(ctx, ens, obs, plan, fair=False):
+        loss, g = plan.spectral_crps(ens.contiguous(), obs.contiguous(), fair=fair, grad=True)
+        ctx.save_for_backward(g)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        return g * gl.to(torch.complex64)[None, :, None, None], None, None, None
+
+
+class SpatialCRPS(torch.autograd.Function):
+    """loss[c] = spatial CRPS of the ensemble fields against the observed field."""
+
+    @staticmethod
+    def forward(ctx, ens, obs, plan, fair=False):
+        loss, g = plan.spatial_crps(ens.contiguous(), obs.contiguous(), fair=fair, grad=True)
+        ctx.save_for_backward(g)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        return g * gl[None, :, None, None], None, None, None
+
+
+class Noise:
+    """Spherical diffusion noise generator (sht_noise_*) on a single-segment
+    plan: per channel length scale kT, time scale lam and amplitude sigma.
+    step() advances the spectral state and returns (state, field)."""
+
+    def __init__(self, plan, kT, lam, sigma, seed=0):
+        d = plan.descs[0]
+        C = d.get("channels", 1)
+        arr = lambda v: (ctypes.c_double * C)(*[float(t) for t in (v if hasattr(v, "__len__") else [v] * C)])
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().sht_noise_create(plan._h, arr(kT), arr(lam), arr(sigma), int(seed),
+                                                ctypes.byref(self._h)))
+        self.state = torch.zeros(plan.spec_shape(), dtype=torch.complex64, device=plan.device)
+
+    def step(self, field=True, out=None):
+        if field and out is None:
+            out = torch.empty(self.plan.grid_shape(), dtype=torch.float32, device=self.plan.device)
+        _lib.check(_lib.load().sht_noise_step(self._h, ctypes.c_void_p(self.state.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr() if field else None),
+                                              _stream_ptr(self.plan.device)))
+        return self.state, out
+
+    def set_step(self, n):
+        _lib.check(_lib.load().sht_noise_set_step(self._h, int(n)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().sht_noise_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Graph:

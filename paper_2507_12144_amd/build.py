@@ -28,7 +28,7 @@ def sources():
     kernels, then the float32 contraction) first, so that the parallel build
     ends soonest."""
     names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
-    order = lambda f: (0 if "_np" in f else 1 if f.startswith("legendre") else 2, f)
+    order = lambda f: (0 if ("_np" in f or "_ncb" in f) else 1 if f.startswith("legendre") else 2, f)
     return [os.path.join(CSRC, f) for f in sorted(names, key=order)]
 
 

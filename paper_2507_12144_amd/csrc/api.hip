@@ -94,6 +94,9 @@ struct Segment {
   double* w = nullptr;
   float* scale_sht = nullptr;  // (2 pi / nlon) w_k, k < nk
   float* scale_one = nullptr;  // 1
+  float* scale_zonal = nullptr;  // 2 pi sin(t_k) (2 pi / nlon)^2, k < nk
+  float* ring_w = nullptr;     // (2 pi / nlon) w_k / (4 pi), k < nlat (spatial CRPS)
+  float* partial = nullptr;    // channels * max(lmax, nlat) (CRPS row sums)
   float2* tw = nullptr;        // e^{-2 pi i j / nlon}
   void* tab_ana = nullptr;     // Legendre table, analysis fragment order
   void* tab_syn = nullptr;     // Legendre table, synthesis fragment order
@@ -147,9 +150,11 @@ struct sht_plan_s {
   sht::SegDev* d_segs = nullptr;
   int2* bwork = nullptr;
   sht::BatchArgs batch{};
-  // schedule (sht_plan_tune): orders per chunk, XCD dealing policy
-  int tune_chunk = 8, tune_policy = 0;
+  // schedule (sht_plan_tune): orders per chunk, XCD dealing policy, field
+  // groups per workgroup of the float32 Legendre kernels
+  int tune_chunk = 8, tune_policy = 0, tune_ncb = 2;
   int graphs = 0;  // live sht_graph_t objects of this plan
+  int noises = 0;  // live sht_noise_t objects of this plan
 };
 
 struct sht_graph_s {
@@ -160,12 +165,19 @@ struct sht_graph_s {
   hipGraphExec_t exec = nullptr;
 };
 
+struct sht_noise_s {
+  sht_plan_s* plan = nullptr;
+  double* sigma_l = nullptr;  // [channels][lmax]
+  double* phi = nullptr;      // [channels]
+  unsigned long long seed = 0, step = 0;
+};
+
 namespace sht {
 namespace {
 
 void free_segment(Segment& s) {
-  void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.tw, s.tab_ana, s.tab_syn, s.tab_off,
-                  s.work};
+  void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.scale_zonal, s.ring_w, s.partial, s.tw, s.tab_ana,
+                  s.tab_syn, s.tab_off, s.work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = Segment{};
@@ -174,6 +186,18 @@ void free_segment(Segment& s) {
 __global__ void ring_scale_kernel(int nk, int nlon, const double* __restrict__ w, float* __restrict__ out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nk) out[k] = static_cast<float>(2.0 * 3.14159265358979323846 / nlon * w[k]);
+}
+
+// Per-ring weights of the zonal PSD (2 pi sin t_k (2 pi / nlon)^2, k < nk)
+// and of the spatial CRPS ((2 pi / nlon) w_k / (4 pi), k < nlat), float64
+// arithmetic rounded once.
+__global__ void ring_weights_kernel(int nlat, int nk, int nlon, const double* __restrict__ s,
+                                    const double* __restrict__ w, float* __restrict__ zonal,
+                                    float* __restrict__ quad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const double dp = 2.0 * 3.14159265358979323846 / nlon;
+  if (k < nk) zonal[k] = static_cast<float>(2.0 * 3.14159265358979323846 * s[k] * dp * dp);
+  if (k < nlat) quad[k] = static_cast<float>(dp * w[k] / (4.0 * 3.14159265358979323846));
 }
 
 // Synthetic tuning input: a hash of the index mapped to [-1, 1).
@@ -241,6 +265,15 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "ring scale kernel");
   if ((rc = upload(&S.scale_one, std::vector<float>(g.nk, 1.0f), st, "ring scale upload")) != SHT_OK) return rc;
+  e = dev_alloc(reinterpret_cast<void**>(&S.scale_zonal), sizeof(float) * g.nk);
+  if (e == hipSuccess) e = dev_alloc(reinterpret_cast<void**>(&S.ring_w), sizeof(float) * d.nlat);
+  if (e != hipSuccess) return hip_fail(e, "ring weight allocation");
+  hipLaunchKernelGGL(ring_weights_kernel, dim3((d.nlat + 63) / 64), dim3(64), 0, st, d.nlat, g.nk, d.nlon, S.s, S.w,
+                     S.scale_zonal, S.ring_w);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "ring weight kernel");
+  e = dev_alloc(reinterpret_cast<void**>(&S.partial), sizeof(float) * d.channels * std::max(d.lmax, d.nlat));
+  if (e != hipSuccess) return hip_fail(e, "score scratch allocation");
 
   // twiddles e^{-2 pi i j / n} in float64, rounded once
   std::vector<float2> tw(d.nlon);
@@ -336,11 +369,14 @@ std::vector<int2> deal_chunks(std::vector<WorkChunk> chunks, int policy, size_t*
 }
 
 // Plan-wide work list of the batched Legendre kernels under the plan's
-// schedule (tune_chunk, tune_policy).
+// schedule (tune_chunk, tune_policy, tune_ncb; the bf16 kernels always take
+// kBatchNcb field groups per workgroup).
 sht_status apply_schedule(sht_plan_s* p) {
+  const int ncb = p->storage == Storage::F32 ? p->tune_ncb : kBatchNcb;
+  p->batch.ncb = ncb;
   std::vector<WorkChunk> chunks;
   for (size_t i = 0; i < p->segs.size(); ++i)
-    add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + kBatchNcb - 1) / kBatchNcb, static_cast<int>(i) << 16,
+    add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + ncb - 1) / ncb, static_cast<int>(i) << 16,
                p->tune_chunk);
   size_t per = 0;
   std::vector<int2> flat = deal_chunks(chunks, p->tune_policy, &per);
@@ -371,6 +407,7 @@ sht_status build_batch(sht_plan_s* p) {
     d.work = S.work;
     d.scale_sht = S.scale_sht;
     d.scale_one = S.scale_one;
+    d.scale_zonal = S.scale_zonal;
     d.tw = S.tw;
     d.grid_off = static_cast<long long>(S.grid_off);
     d.spec_off = static_cast<long long>(S.spec_off);
@@ -396,7 +433,7 @@ hipStream_t pick_stream(const sht_plan_s* p, void* s) {
   return s ? static_cast<hipStream_t>(s) : p->stream;
 }
 
-enum Kind { K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5 };
+enum Kind { K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5, K_SCORE = 6, K_NOISE = 7 };
 
 hipEvent_t take_event(sht_plan_s* p) {
   if (!p->event_pool.empty()) {
@@ -540,7 +577,8 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
 
 sht_status sht_plan_destroy(sht_plan_t plan) {
   if (!plan) return SHT_OK;
-  if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs first");
+  if (plan->graphs > 0 || plan->noises > 0)
+    return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs and noise generators first");
   sht_status rc = SHT_OK;
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
@@ -622,6 +660,35 @@ sht_status sht_channel_mix_weight_grad(sht_plan_t plan, const void* g, const voi
                                           static_cast<const float2*>(x), static_cast<float2*>(dW), st);
   });
   if (e != hipSuccess) return hip_fail(e, "channel mix weight gradient launch");
+  return SHT_OK;
+}
+
+sht_status sht_isotropic_filter(sht_plan_t plan, const void* k, const void* in, void* out, int adjoint,
+                                void* hip_stream) {
+  if (!plan || !k || !in || !out) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (in == out) return fail(SHT_ERR_INVALID_ARG, "input and output must not alias");
+  if (plan->segs.size() != 1) return fail(SHT_ERR_INVALID_ARG, "the filter needs a single-segment plan");
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_MIX, st, [&] {
+    return launch_isotropic_filter(d.batch, d.channels, d.lmax, d.mmax, static_cast<const float2*>(k),
+                                   static_cast<const float2*>(in), static_cast<float2*>(out), adjoint, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "isotropic filter launch");
+  return SHT_OK;
+}
+
+sht_status sht_isotropic_filter_grad(sht_plan_t plan, const void* g, const void* x, void* dk, void* hip_stream) {
+  if (!plan || !g || !x || !dk) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (dk == g || dk == x) return fail(SHT_ERR_INVALID_ARG, "dk must alias neither input");
+  if (plan->segs.size() != 1) return fail(SHT_ERR_INVALID_ARG, "the filter needs a single-segment plan");
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_MIX, st, [&] {
+    return launch_isotropic_filter_grad(d.batch, d.channels, d.lmax, d.mmax, static_cast<const float2*>(g),
+                                        static_cast<const float2*>(x), static_cast<float2*>(dk), st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "isotropic filter gradient launch");
   return SHT_OK;
 }
 
@@ -708,13 +775,21 @@ sht_status sht_graph_destroy(sht_graph_t graph) {
 sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, double* best_ms) {
   if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
   if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs before tuning it");
+  // Candidates: field groups per workgroup (float32 kernels only) x orders
+  // per chunk x XCD dealing.  The default comes first: every other one must
+  // reproduce its outputs bit for bit.
   struct Cand {
-    int chunk, policy;
+    int chunk, policy, ncb;
   };
-  const std::vector<Cand> cands = {{8, 0}, {4, 0}, {16, 0}, {32, 0}, {8, 1}, {16, 1}};
+  std::vector<Cand> cands = {{8, 0, 2}, {4, 0, 2}, {16, 0, 2}, {32, 0, 2}, {8, 1, 2}, {16, 1, 2}};
+  if (plan->storage == Storage::F32)
+    for (int ncb : {3, 4})
+      for (Cand c : {Cand{8, 0, ncb}, Cand{4, 0, ncb}, Cand{16, 0, ncb}, Cand{8, 1, ncb}})
+        if (legendre_ncb_supported(ncb)) cands.push_back(c);
   auto apply = [&](const Cand& c) {
     plan->tune_chunk = c.chunk;
     plan->tune_policy = c.policy;
+    plan->tune_ncb = c.ncb;
     return apply_schedule(plan);
   };
   // cache key: arch | descriptors | precision
@@ -728,7 +803,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
              static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
     key += buf;
   }
-  key += "|" + std::to_string(static_cast<int>(plan->prec));
+  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v2";
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -795,7 +870,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   sht_status rc = SHT_OK;
   int best = 0;
   float best_t = 0.f;
-  const Cand saved{plan->tune_chunk, plan->tune_policy};
+  const Cand saved{plan->tune_chunk, plan->tune_policy, plan->tune_ncb};
   for (size_t ci = 0; ci < cands.size() && rc == SHT_OK; ++ci) {
     rc = apply(cands[ci]);
     if (rc != SHT_OK) break;
@@ -851,6 +926,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   if (rc != SHT_OK) {
     plan->tune_chunk = saved.chunk;
     plan->tune_policy = saved.policy;
+    plan->tune_ncb = saved.ncb;
     (void)apply_schedule(plan);
     return rc;
   }
@@ -862,6 +938,26 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   }
   if (chosen) *chosen = best;
   if (best_ms) *best_ms = best_t;
+  return SHT_OK;
+}
+
+sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb) {
+  if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs before changing its schedule");
+  if (chunk < 1 || chunk > 64) return fail(SHT_ERR_INVALID_ARG, "chunk must be in [1, 64]");
+  if (policy != 0 && policy != 1) return fail(SHT_ERR_INVALID_ARG, "policy must be 0 or 1");
+  if (!legendre_ncb_supported(ncb)) return fail(SHT_ERR_INVALID_ARG, "ncb must be 2, 3 or 4");
+  plan->tune_chunk = chunk;
+  plan->tune_policy = policy;
+  plan->tune_ncb = ncb;
+  return apply_schedule(plan);
+}
+
+sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb) {
+  if (!plan || !chunk || !policy || !ncb) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  *chunk = plan->tune_chunk;
+  *policy = plan->tune_policy;
+  *ncb = plan->batch.ncb;
   return SHT_OK;
 }
 
@@ -889,6 +985,150 @@ sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, 
   }
   plan->pending.clear();
   return rc;
+}
+
+// ---- scores, spectra and noise (single-segment plans) ---------------------
+
+static sht_status single_segment(sht_plan_t plan, const char* what) {
+  if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->segs.size() != 1) return fail(SHT_ERR_INVALID_ARG, "%s needs a single-segment plan", what);
+  return SHT_OK;
+}
+
+sht_status sht_psd(sht_plan_t plan, const void* y, float* out, void* hip_stream) {
+  sht_status rc = single_segment(plan, "sht_psd");
+  if (rc != SHT_OK) return rc;
+  if (!y || !out) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  const long long F = static_cast<long long>(d.batch) * d.channels;
+  hipError_t e = timed(plan, K_SCORE, st, [&] {
+    return launch_psd(static_cast<const float2*>(y), F, d.lmax, d.mmax, out, st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "psd launch");
+  return SHT_OK;
+}
+
+sht_status sht_zonal_psd(sht_plan_t plan, const float* x, float* out, void* hip_stream) {
+  sht_status rc = single_segment(plan, "sht_zonal_psd");
+  if (rc != SHT_OK) return rc;
+  if (!x || !out) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (static_cast<const void*>(x) == static_cast<const void*>(out))
+    return fail(SHT_ERR_INVALID_ARG, "input and output must not alias");
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_SCORE, st, [&] { return launch_zonal_psd(plan->batch, x, out, st); });
+  if (e != hipSuccess) return hip_fail(e, "zonal psd launch");
+  return SHT_OK;
+}
+
+static sht_status crps_common(sht_plan_t plan, bool spectral, const void* ens, const void* obs, int fair, int l_hi,
+                              float* loss, void* grad, void* hip_stream) {
+  sht_status rc = single_segment(plan, spectral ? "sht_spectral_crps" : "sht_spatial_crps");
+  if (rc != SHT_OK) return rc;
+  if (!ens || !obs || !loss) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (grad == ens || grad == obs) return fail(SHT_ERR_INVALID_ARG, "grad must alias neither input");
+  const Segment& S = plan->segs[0];
+  const sht_desc& d = S.d;
+  if (d.batch > crps_max_members())
+    return fail(SHT_ERR_UNSUPPORTED, "at most %d ensemble members (plan batch)", crps_max_members());
+  if (fair && d.batch < 2) return fail(SHT_ERR_INVALID_ARG, "the fair CRPS needs at least two members");
+  CrpsShape sh;
+  sh.spectral = spectral;
+  sh.members = d.batch;
+  sh.channels = d.channels;
+  sh.rows = spectral ? d.lmax : d.nlat;
+  sh.cols = spectral ? d.mmax : d.nlon;
+  sh.l_hi = l_hi > 0 ? l_hi : std::min(d.lmax - 1, d.nlat / 2);
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_SCORE, st, [&] {
+    return launch_crps(sh, static_cast<const float*>(ens), static_cast<const float*>(obs), S.ring_w, fair != 0,
+                       S.partial, loss, static_cast<float*>(grad), st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "crps launch");
+  return SHT_OK;
+}
+
+sht_status sht_spectral_crps(sht_plan_t plan, const void* ens, const void* obs, int fair, int l_hi, float* loss,
+                             void* grad, void* hip_stream) {
+  return crps_common(plan, true, ens, obs, fair, l_hi, loss, grad, hip_stream);
+}
+
+sht_status sht_spatial_crps(sht_plan_t plan, const float* ens, const float* obs, int fair, float* loss, float* grad,
+                            void* hip_stream) {
+  return crps_common(plan, false, ens, obs, fair, 0, loss, grad, hip_stream);
+}
+
+sht_status sht_noise_create(sht_plan_t plan, const double* kT, const double* lambda, const double* sigma,
+                            unsigned long long seed, sht_noise_t* out) {
+  if (!out) return fail(SHT_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  sht_status rc = single_segment(plan, "sht_noise_create");
+  if (rc != SHT_OK) return rc;
+  if (!kT || !lambda || !sigma) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  const sht_desc& d = plan->segs[0].d;
+  const int C = d.channels, L = d.lmax;
+  std::vector<double> sl(static_cast<size_t>(C) * L, 0.0), ph(C);
+  for (int c = 0; c < C; ++c) {
+    if (!(kT[c] > 0.0) || !(lambda[c] > 0.0) || !(sigma[c] >= 0.0) || !std::isfinite(kT[c]) ||
+        !std::isfinite(lambda[c]) || !std::isfinite(sigma[c]))
+      return fail(SHT_ERR_INVALID_ARG, "channel %d: need k_T > 0, lambda > 0, sigma >= 0", c);
+    if (L < 2) return fail(SHT_ERR_INVALID_ARG, "the noise needs lmax >= 2 (degrees l >= 1)");
+    // phi = e^-lambda, sigma_l = F_0 e^{-k_T l (l+1) / 2},
+    // F_0 = sigma sqrt(2 pi (1 - phi^2) / sum_{0 < l < lmax} (2l + 1) e^{-k_T l (l+1)})
+    const double phi = std::exp(-lambda[c]);
+    double den = 0.0;
+    for (int l = 1; l < L; ++l) den += (2.0 * l + 1.0) * std::exp(-kT[c] * l * (l + 1.0));
+    const double F0 = sigma[c] * std::sqrt(2.0 * M_PI * (1.0 - phi * phi) / den);
+    for (int l = 1; l < L; ++l) sl[static_cast<size_t>(c) * L + l] = F0 * std::exp(-0.5 * kT[c] * l * (l + 1.0));
+    ph[c] = phi;
+  }
+  auto* n = new (std::nothrow) sht_noise_s();
+  if (!n) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
+  n->plan = plan;
+  n->seed = seed;
+  rc = upload(&n->sigma_l, sl, plan->stream, "noise parameters");
+  if (rc == SHT_OK) rc = upload(&n->phi, ph, plan->stream, "noise parameters");
+  if (rc != SHT_OK) {
+    if (n->sigma_l) (void)hipFree(n->sigma_l);
+    if (n->phi) (void)hipFree(n->phi);
+    delete n;
+    return rc;
+  }
+  plan->noises += 1;  // the plan must outlive the generator
+  *out = n;
+  return SHT_OK;
+}
+
+sht_status sht_noise_step(sht_noise_t noise, void* state, float* z, void* hip_stream) {
+  if (!noise || !state) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  sht_plan_s* plan = noise->plan;
+  const sht_desc& d = plan->segs[0].d;
+  hipStream_t st = pick_stream(plan, hip_stream);
+  hipError_t e = timed(plan, K_NOISE, st, [&] {
+    return launch_noise_step(d.batch, d.channels, d.lmax, d.mmax, noise->sigma_l, noise->phi, noise->seed,
+                             noise->step, static_cast<float2*>(state), st);
+  });
+  if (e != hipSuccess) return hip_fail(e, "noise launch");
+  noise->step += 1;
+  if (z) return run(plan, Op::ISHT, state, z, hip_stream);
+  return SHT_OK;
+}
+
+sht_status sht_noise_set_step(sht_noise_t noise, unsigned long long step) {
+  if (!noise) return fail(SHT_ERR_INVALID_ARG, "noise is NULL");
+  noise->step = step;
+  return SHT_OK;
+}
+
+sht_status sht_noise_destroy(sht_noise_t noise) {
+  if (!noise) return SHT_OK;
+  hipError_t e = hipStreamSynchronize(noise->plan->stream);
+  (void)hipFree(noise->sigma_l);
+  (void)hipFree(noise->phi);
+  noise->plan->noises -= 1;
+  delete noise;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return SHT_OK;
 }
 
 const char* sht_status_string(sht_status s) {

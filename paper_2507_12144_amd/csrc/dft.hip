@@ -370,7 +370,8 @@ __device__ __forceinline__ size_t wrow(const DftArgs& a, int m, int p, int g, in
 template <class FFT>
 __device__ __forceinline__ void dft_forward_body(const DftArgs& a, const Item& it, const float* __restrict__ x,
                                                  float* __restrict__ W, const float2* __restrict__ tw,
-                                                 const float* __restrict__ ring_scale, float2* lds) {
+                                                 const float* __restrict__ ring_scale, float2* lds,
+                                                 float* __restrict__ zonal) {
   const int N = a.nlon;
   const int kk = it.kk;
   const int ks = a.nlat - 1 - kk;
@@ -443,6 +444,23 @@ __device__ __forceinline__ void dft_forward_body(const DftArgs& a, const Item& i
   __syncthreads();
   const float2* Z = FFT::run(lds, a, tw, -1.f);
   const float sc = ring_scale[kk];
+  if (zonal) {
+    // zonal power spectra of the two rings: sc |X|^2 with the zonal scale
+    for (int m = threadIdx.x; m < a.mmax; m += NT) {
+#pragma unroll
+      for (int fl = 0; fl < FGW; ++fl) {
+        const int fi = f0 + fl;
+        if (fi >= a.F) continue;
+        const float2 zm = Z[fl * N + m];
+        const float2 zr = Z[fl * N + (m == 0 ? 0 : N - m)];
+        const float2 xn = make_float2(0.5f * (zm.x + zr.x), 0.5f * (zm.y - zr.y));
+        const float2 xs = make_float2(0.5f * (zm.y + zr.y), -0.5f * (zm.x - zr.x));
+        zonal[(static_cast<size_t>(fi) * a.nlat + kk) * a.mmax + m] = sc * (xn.x * xn.x + xn.y * xn.y);
+        if (!eq) zonal[(static_cast<size_t>(fi) * a.nlat + ks) * a.mmax + m] = sc * (xs.x * xs.x + xs.y * xs.y);
+      }
+    }
+    return;
+  }
   for (int m = threadIdx.x; m < a.mmax; m += NT) {
     float Sv[8], Av[8];
 #pragma unroll
@@ -615,8 +633,10 @@ __device__ __forceinline__ int segment_of(const SegDev* __restrict__ segs, int n
   return s;
 }
 
+// mode 0: unit ring scale, 1: (2 pi / nlon) w_k, 2: zonal PSD into `zonal`
 __global__ __launch_bounds__(NT) void dft_forward_batched(const SegDev* __restrict__ segs, int nseg, int total,
-                                                          const float* __restrict__ x, int sht_scale) {
+                                                          const float* __restrict__ x, int mode,
+                                                          float* __restrict__ zonal) {
   extern __shared__ float2 lds[];
   const int slot = batched_slot(total);
   if (slot >= total) return;
@@ -625,13 +645,14 @@ __global__ __launch_bounds__(NT) void dft_forward_batched(const SegDev* __restri
   const Item it = item_of(a, slot - sd.dft_begin);
   if (!it.valid) return;
   const float* xs = x + sd.grid_off;
-  const float* scale = sht_scale ? sd.scale_sht : sd.scale_one;
+  const float* scale = mode == 1 ? sd.scale_sht : mode == 2 ? sd.scale_zonal : sd.scale_one;
+  float* zs = mode == 2 ? zonal : nullptr;
   switch (sd.g.nlon) {
-    case 1440: dft_forward_body<F1440>(a, it, xs, sd.work, sd.tw, scale, lds); break;
-    case 720: dft_forward_body<F720>(a, it, xs, sd.work, sd.tw, scale, lds); break;
-    case 360: dft_forward_body<F360>(a, it, xs, sd.work, sd.tw, scale, lds); break;
-    case 64: dft_forward_body<F64>(a, it, xs, sd.work, sd.tw, scale, lds); break;
-    default: dft_forward_body<GenericFFT>(a, it, xs, sd.work, sd.tw, scale, lds); break;
+    case 1440: dft_forward_body<F1440>(a, it, xs, sd.work, sd.tw, scale, lds, zs); break;
+    case 720: dft_forward_body<F720>(a, it, xs, sd.work, sd.tw, scale, lds, zs); break;
+    case 360: dft_forward_body<F360>(a, it, xs, sd.work, sd.tw, scale, lds, zs); break;
+    case 64: dft_forward_body<F64>(a, it, xs, sd.work, sd.tw, scale, lds, zs); break;
+    default: dft_forward_body<GenericFFT>(a, it, xs, sd.work, sd.tw, scale, lds, zs); break;
   }
 }
 
@@ -697,7 +718,14 @@ hipError_t prepare_dft_kernels(size_t lds_bytes) {
 hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool sht_scale, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
   hipLaunchKernelGGL(dft_forward_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x,
-                     sht_scale ? 1 : 0);
+                     sht_scale ? 1 : 0, static_cast<float*>(nullptr));
+  return hipGetLastError();
+}
+
+hipError_t launch_zonal_psd(const BatchArgs& b, const float* x, float* out, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((b.dft_total + 7) / 8 * 8);
+  hipLaunchKernelGGL(dft_forward_batched, dim3(blocks), dim3(NT), b.dft_lds, st, b.segs, b.nseg, b.dft_total, x, 2,
+                     out);
   return hipGetLastError();
 }
 

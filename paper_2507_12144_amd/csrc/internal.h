@@ -60,6 +60,7 @@ struct SegDev {
   float* work;             // workspace W[m][p][g][k][16] of the segment
   const float* scale_sht;  // (2 pi / nlon) w_k
   const float* scale_one;  // 1
+  const float* scale_zonal;  // 2 pi sin(t_k) (2 pi / nlon)^2
   const float2* tw;        // e^{-2 pi i j / nlon}
   long long grid_off;      // first float of the segment in grid buffers
   long long spec_off;      // first complex of the segment in spectral buffers
@@ -77,8 +78,10 @@ struct BatchArgs {
   int work_per;
   int dft_total;           // DFT items of all segments
   size_t dft_lds;          // dynamic LDS of the batched DFT kernels
+  int ncb;                 // field groups per column chunk (workgroup) of the Legendre kernels
 };
-// Field groups per column chunk of the batched Legendre kernels.
+// Field groups per column chunk of the bf16 Legendre kernels (the float32
+// kernels take BatchArgs::ncb, see legendre_ncb_supported).
 constexpr int kBatchNcb = 2;
 // Dynamic LDS the DFT kernels need for ring width nlon; prepare_dft_kernels
 // raises the batched kernels' dynamic-LDS limit to lds_bytes (call once per
@@ -93,6 +96,11 @@ hipError_t prepare_dft_kernels(size_t lds_bytes);
 // synthesises sum_m c_m Re(Y e^{i m p}) with c_0 = 1, c_m = c_rest, scales
 // ring k and writes the grid tensor.  x is the plan-wide grid buffer.
 hipError_t launch_dft_forward_batched(const BatchArgs& b, const float* x, bool sht_scale, hipStream_t st);
+// Zonal power spectral density (App. F.7, eq. zonal_psd) of every ring of a
+// single-segment plan: the forward ring DFT with its epilogue writing
+// out[f][k][m] = 2 pi sin(t_k) |(2 pi / nlon) sum_j x[f][k][j] e^{-2 pi i j m / nlon}|^2
+// for m < mmax instead of the folded spectrum.
+hipError_t launch_zonal_psd(const BatchArgs& b, const float* x, float* out, hipStream_t st);
 hipError_t launch_dft_inverse_batched(const BatchArgs& b, float* x, bool sht_scale, float c_rest, hipStream_t st);
 // Batched float32 Legendre steps (y is the plan-wide spectral buffer):
 // analysis y[f][l][m] = mscale_m sum_k P^_l^m(x_k) W[m][p][g][k][..]
@@ -104,11 +112,38 @@ hipError_t launch_legendre_synthesis_batched(const BatchArgs& b, const float2* y
 // ---- legendre.hip --------------------------------------------------------
 // Ring padding the contraction kernels support for nk rings (-1: none).
 int legendre_ring_pad(int nk);
+// Field groups per workgroup the float32 contraction kernels are built for.
+bool legendre_ncb_supported(int ncb);
 // bf16 forms (legendre_bf16*.hip): the contract of the batched float32
 // steps, with the table stored as `planes` bf16 planes.
 hipError_t launch_legendre_analysis_bf16_batched(const BatchArgs& b, int planes, float2* y, float c_rest,
                                                  hipStream_t st);
 hipError_t launch_legendre_synthesis_bf16_batched(const BatchArgs& b, int planes, const float2* y, hipStream_t st);
+
+// ---- scores.hip ----------------------------------------------------------
+// Angular PSD (App. F.7, eq. psd): out[f][l] = sum_{m <= min(l, mmax-1)} c_m |y[f][l][m]|^2.
+hipError_t launch_psd(const float2* y, long long F, int lmax, int mmax, float* out, hipStream_t st);
+// Ensemble CRPS loss terms (App. D.4, App. E.1).  Spectral: rows = lmax,
+// cols = mmax, complex elements, weights c_m for 1 <= l <= l_hi, m <= l.
+// Spatial: rows = nlat, cols = nlon, real elements, weight ring_w[k].
+struct CrpsShape {
+  bool spectral;
+  int members, channels, rows, cols, l_hi;
+};
+int crps_max_members();
+// loss[c] (float, channels entries) and, with grad != nullptr, the gradient
+// with respect to every member; partial: channels * rows floats of scratch.
+hipError_t launch_crps(const CrpsShape& s, const float* ens, const float* obs, const float* ring_w, bool fair,
+                       float* partial, float* loss, float* grad, hipStream_t st);
+
+// ---- noise.hip -----------------------------------------------------------
+// One step of the spherical diffusion process (App. B.7, eq.
+// spherical_diffusion) on the coefficients y[b][c][l][m] (complex64,
+// in place): Philox4x64-10 normals at counter (index, step, 0, 0), key
+// (seed, 0); sigma_l[c][l] and phi[c] in float64.  step == 0 draws the
+// stationary start.
+hipError_t launch_noise_step(int batch, int channels, int lmax, int mmax, const double* sigma_l, const double* phi,
+                             unsigned long long seed, unsigned long long step, float2* y, hipStream_t st);
 
 // ---- mix.hip -------------------------------------------------------------
 // dW[l][c'][c] = sum_{b, m <= min(l, mmax-1)} g[b][c'][l][m] conj(x[b][c][l][m])
@@ -116,5 +151,11 @@ hipError_t launch_channel_mix_weight_grad(int batch, int channels, int lmax, int
                                           const float2* x, float2* dW, hipStream_t stream);
 hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const float2* W,
                               const float2* in, float2* out, int adjoint, hipStream_t stream);
+// out[b][c][l][m] = k[c][l] in[b][c][l][m] (adjoint: conj(k)), 0 for m > l;
+// dk[c][l] = sum_{b, m <= min(l, mmax-1)} g conj(x).
+hipError_t launch_isotropic_filter(int batch, int channels, int lmax, int mmax, const float2* k, const float2* in,
+                                   float2* out, int adjoint, hipStream_t stream);
+hipError_t launch_isotropic_filter_grad(int batch, int channels, int lmax, int mmax, const float2* g,
+                                        const float2* x, float2* dk, hipStream_t stream);
 
 }  // namespace sht

@@ -233,6 +233,58 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
   });
 }
 
+// Isotropic per-channel filter, the single-channel form of eq.
+// s2_spectral_conv: out[b,c,l,m] = k[c,l] in[b,c,l,m] (adjoint: conj(k)),
+// 0 for m > l.  Elementwise and HBM-bound: one thread per coefficient,
+// consecutive threads on consecutive m.
+__global__ __launch_bounds__(256) void isotropic_filter_kernel(long long total, int C, int lmax, int mmax,
+                                                               const float2* __restrict__ k,
+                                                               const float2* __restrict__ in,
+                                                               float2* __restrict__ out, int adjoint) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int m = static_cast<int>(i % mmax);
+  const long long r = i / mmax;
+  const int l = static_cast<int>(r % lmax);
+  const int c = static_cast<int>((r / lmax) % C);
+  if (m > l) {
+    out[i] = make_float2(0.f, 0.f);
+    return;
+  }
+  const float2 kv = k[static_cast<long long>(c) * lmax + l];
+  const float ki = adjoint ? -kv.y : kv.y;
+  const float2 x = in[i];
+  out[i] = make_float2(kv.x * x.x - ki * x.y, kv.x * x.y + ki * x.x);
+}
+
+// Filter gradient dk[c,l] = sum_b sum_{m <= min(l, mmax-1)} g conj(x): one
+// wave per (c, l); lanes over m, members in order, a fixed-order wave sum.
+__global__ __launch_bounds__(256) void isotropic_filter_grad_kernel(int B, int C, int lmax, int mmax,
+                                                                    const float2* __restrict__ g,
+                                                                    const float2* __restrict__ x,
+                                                                    float2* __restrict__ dk) {
+  const int lane = threadIdx.x & 63;
+  const long long row = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);  // c * lmax + l
+  if (row >= static_cast<long long>(C) * lmax) return;
+  const int l = static_cast<int>(row % lmax);
+  const int mend = min(l + 1, mmax);
+  float re = 0.f, im = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const long long base = (static_cast<long long>(b) * C * lmax + row) * mmax;
+    for (int m = lane; m < mend; m += 64) {
+      const float2 gv = g[base + m], xv = x[base + m];
+      re += gv.x * xv.x + gv.y * xv.y;
+      im += gv.y * xv.x - gv.x * xv.y;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) dk[row] = make_float2(re, im);
+}
+
 }  // namespace
 
 hipError_t launch_channel_mix_weight_grad(int batch, int channels, int lmax, int mmax, const float2* g,
@@ -261,6 +313,26 @@ hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(mix_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch,
                      channels, lmax, mmax, out);
+  return hipGetLastError();
+}
+
+}  // namespace sht
+
+namespace sht {
+
+hipError_t launch_isotropic_filter(int batch, int channels, int lmax, int mmax, const float2* k, const float2* in,
+                                   float2* out, int adjoint, hipStream_t stream) {
+  const long long total = static_cast<long long>(batch) * channels * lmax * mmax;
+  hipLaunchKernelGGL(isotropic_filter_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
+                     total, channels, lmax, mmax, k, in, out, adjoint);
+  return hipGetLastError();
+}
+
+hipError_t launch_isotropic_filter_grad(int batch, int channels, int lmax, int mmax, const float2* g,
+                                        const float2* x, float2* dk, hipStream_t stream) {
+  const long long rows = static_cast<long long>(channels) * lmax;
+  hipLaunchKernelGGL(isotropic_filter_grad_kernel, dim3(static_cast<unsigned>((rows + 3) / 4)), dim3(256), 0, stream,
+                     batch, channels, lmax, mmax, g, x, dk);
   return hipGetLastError();
 }
 

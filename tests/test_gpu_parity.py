@@ -702,3 +702,28 @@ def test_tune_parity_and_cache(pkg, tmp_path, prec):
     assert np.array_equal(plan2.sht(u).cpu().numpy()[masks[0]], before[0][masks[0]])
     plan.close()
     plan2.close()
+
+
+@pytest.mark.parametrize("shape", [(721, 1440, 720, 720, 0, 1, 72), (360, 720, 360, 360, 1, 4, 40),
+                                   (181, 360, 180, 180, 0, 1, 37)],
+                         ids=lambda s: f"{s[0]}x{s[1]}_F{s[5] * s[6]}")
+def test_field_groups_per_workgroup_are_bitwise_equal(pkg, shape):
+    """The float32 kernels with 2, 3 and 4 field groups per workgroup (a
+    tuning choice) give the same bits for all four transforms, also with a
+    ragged last column chunk."""
+    _say("ncb schedules", shape)
+    nlat, nlon, L, M, grid, B, C = shape
+    plan = _plan(pkg, *shape)
+    u = _to_dev(synth.grid_normal(31, (B, C, nlat, nlon)), torch.float32)
+    a = _to_dev(synth.coefficients(32, B, C, L, M), torch.complex64)
+    ref = None
+    for ncb in (2, 3, 4):
+        plan.set_schedule(8, 0, ncb)
+        assert plan.schedule() == (8, 0, ncb)
+        outs = [plan.sht(u), plan.isht(a), plan.sht_T(a), plan.isht_T(u)]
+        if ref is None:
+            ref = outs
+        else:
+            for o, r in zip(outs, ref):
+                assert torch.equal(o, r), ncb
+    plan.close()
