@@ -203,6 +203,20 @@ sht_status sht_zonal_psd(sht_plan_t plan, const float* x, float* out, void* hip_
 sht_status sht_spectral_crps(sht_plan_t plan, const void* ens, const void* obs, int fair, int l_hi, float* loss,
                              void* grad, void* hip_stream);
 
+/* Allocation-free form of sht_spectral_crps, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): no plan -- the shape comes from
+ * *desc (batch = the N ensemble members) -- and the per-row sums go to a
+ * static device array of the library (1 MiB on every GPU the library runs
+ * on, held until the process ends) instead of plan-owned scratch.  Limits:
+ * channels * lmax <= 262144, 1 <= batch <= 64 (batch >= 2 when fair).
+ * Calls no hipMalloc or hipFree.  All calls on one GPU share that array:
+ * calls that overlap in time on one GPU race.  Arguments, outputs and
+ * errors as for sht_spectral_crps (SHT_ERR_UNSUPPORTED beyond the limits,
+ * checked before any HIP call); the outputs equal sht_spectral_crps's. */
+sht_status sht_spectral_crps_noalloc(const sht_desc* desc, const void* ens, const void* obs, int fair, int l_hi,
+                                     float* loss, void* grad, void* hip_stream);
+
 /* Spatial CRPS loss term (App. E.1, eq. spatial_loss): the point-wise CRPS
  * of the N = batch members averaged over the sphere,
  *   loss[c] = (1/4 pi) sum_k sum_j (2 pi/nlon) w_k CRPS_kj,

@@ -18,7 +18,7 @@ EXPORTS = ["sht_plan", "sht_plan_destroy", "sht_plan_segment", "sht_plan_sizes",
            "sht_channel_mix_weight_grad", "sht_isotropic_filter", "sht_isotropic_filter_grad", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy", "sht_plan_tune",
            "sht_plan_set_schedule", "sht_plan_get_schedule",
            "sht_plan_timing", "sht_plan_timing_read", "sht_psd", "sht_zonal_psd", "sht_spectral_crps",
-           "sht_spatial_crps", "sht_noise_create", "sht_noise_step", "sht_noise_set_step", "sht_noise_destroy",
+           "sht_spectral_crps_noalloc", "sht_spatial_crps", "sht_noise_create", "sht_noise_step", "sht_noise_set_step", "sht_noise_destroy",
            "sht_status_string", "sht_last_error"]
 
 OPS = {"sht": 0, "isht": 1, "sht_T": 2, "isht_T": 3}
@@ -72,6 +72,7 @@ def load():
     lib.sht_zonal_psd.argtypes = [vp, vp, vp, vp]
     lib.sht_spectral_crps.argtypes = [vp, vp, vp, ip, ip, vp, vp, vp]
     lib.sht_spatial_crps.argtypes = [vp, vp, vp, ip, vp, vp, vp]
+    lib.sht_spectral_crps_noalloc.argtypes = [ctypes.POINTER(ShtDesc), vp, vp, ip, ip, vp, vp, vp]
     dp = ctypes.POINTER(ctypes.c_double)
     lib.sht_noise_create.argtypes = [vp, dp, dp, dp, ctypes.c_ulonglong, ctypes.POINTER(vp)]
     lib.sht_noise_step.argtypes = [vp, vp, vp, vp]

@@ -1058,6 +1058,37 @@ sht_status sht_spatial_crps(sht_plan_t plan, const float* ens, const float* obs,
   return crps_common(plan, false, ens, obs, fair, 0, loss, grad, hip_stream);
 }
 
+sht_status sht_spectral_crps_noalloc(const sht_desc* desc, const void* ens, const void* obs, int fair, int l_hi,
+                                     float* loss, void* grad, void* hip_stream) {
+  if (!desc) return fail(SHT_ERR_INVALID_ARG, "desc is NULL");
+  sht_status rc = validate_desc(*desc, 0);
+  if (rc != SHT_OK) return rc;
+  if (!ens || !obs || !loss) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+  if (grad == ens || grad == obs) return fail(SHT_ERR_INVALID_ARG, "grad must alias neither input");
+  if (desc->batch > crps_max_members())
+    return fail(SHT_ERR_UNSUPPORTED, "at most %d ensemble members (batch)", crps_max_members());
+  if (fair && desc->batch < 2) return fail(SHT_ERR_INVALID_ARG, "the fair CRPS needs at least two members");
+  const size_t need = static_cast<size_t>(desc->channels) * desc->lmax;
+  if (need > crps_static_scratch_floats())
+    return fail(SHT_ERR_UNSUPPORTED, "channels * lmax = %zu exceeds the static scratch of %zu floats", need,
+                crps_static_scratch_floats());
+  // --- first HIP call below this line ---
+  float* scratch = nullptr;
+  hipError_t e = crps_static_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "static scratch address");
+  CrpsShape sh;
+  sh.spectral = true;
+  sh.members = desc->batch;
+  sh.channels = desc->channels;
+  sh.rows = desc->lmax;
+  sh.cols = desc->mmax;
+  sh.l_hi = l_hi > 0 ? l_hi : std::min(desc->lmax - 1, desc->nlat / 2);
+  e = launch_crps(sh, static_cast<const float*>(ens), static_cast<const float*>(obs), nullptr, fair != 0, scratch,
+                  loss, static_cast<float*>(grad), static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "crps launch");
+  return SHT_OK;
+}
+
 sht_status sht_noise_create(sht_plan_t plan, const double* kT, const double* lambda, const double* sigma,
                             unsigned long long seed, sht_noise_t* out) {
   if (!out) return fail(SHT_ERR_INVALID_ARG, "out is NULL");

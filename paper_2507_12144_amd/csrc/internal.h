@@ -131,6 +131,10 @@ struct CrpsShape {
   int members, channels, rows, cols, l_hi;
 };
 int crps_max_members();
+// The allocation-free form's scratch: a static device array (floats) and its
+// address on the current device (looked up once per device).
+size_t crps_static_scratch_floats();
+hipError_t crps_static_scratch(float** out);
 // loss[c] (float, channels entries) and, with grad != nullptr, the gradient
 // with respect to every member; partial: channels * rows floats of scratch.
 hipError_t launch_crps(const CrpsShape& s, const float* ens, const float* obs, const float* ring_w, bool fair,

@@ -16,6 +16,8 @@
 // each thread holding the N member values of its element in VGPRs.  Sums are
 // taken in a fixed order (per thread, then a fixed tree in LDS, then per
 // channel over the rows in order), so results are bitwise reproducible.
+#include <mutex>
+
 #include "internal.h"
 
 namespace sht {
@@ -23,6 +25,15 @@ namespace {
 
 constexpr int kRowThreads = 256;
 
+// Scratch of the allocation-free CRPS entry point: the per-row sums, in a
+// file-scope device array that every GPU the library runs on holds from
+// module load to process end.  Host code uses the per-device address from
+// hipGetSymbolAddress, never the array's name.
+constexpr size_t kStaticScratchFloats = size_t(1) << 18;  // 1 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
 
 // Fixed-order sum of one value per thread of a 256-thread workgroup.
 __device__ __forceinline__ float block_sum(float v, float* red) {
@@ -185,6 +196,25 @@ hipError_t launch_psd(const float2* y, long long F, int lmax, int mmax, float* o
 }
 
 int crps_max_members() { return 64; }
+
+size_t crps_static_scratch_floats() { return kStaticScratchFloats; }
+
+hipError_t crps_static_scratch(float** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_crps(const CrpsShape& s, const float* ens, const float* obs, const float* ring_w, bool fair,
                        float* partial, float* loss, float* grad, hipStream_t st) {
