@@ -52,9 +52,13 @@ def parse():
                          "graph-replayed, with p50/p99 replay latency")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (batched workload)")
     ap.add_argument("--schedule", default=None,
-                    help="chunk,policy,ncb: an explicit work schedule for the Legendre kernels (results unchanged)")
+                    help="chunk,policy,ncb[,staged]: an explicit work schedule for the Legendre kernels "
+                         "(results unchanged)")
     ap.add_argument("--tune", action="store_true", help="run the schedule autotuner before timing (sht721)")
     ap.add_argument("--block-batch", type=int, default=4, help="sfno_block: batch (ensemble members)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="sht721: skip the graph replay and the peak microbenchmarks after the timed region, so "
+                         "that a profiler sees only the plan build, the warm-up and the timed steps")
     ap.add_argument("--block-channels", type=int, default=256, help="sfno_block: channels (677 in the model)")
     return ap.parse_args()
 
@@ -91,7 +95,7 @@ def profiled_traffic(kind, precision):
     has changed since the counters were taken."""
     import glob
     import hashlib
-    src_file = "legendre.hip" if precision == "fp32" else "legendre_bf16.h"
+    src_file = "legendre.h" if precision == "fp32" else "legendre_bf16.h"
     src_key = "legendre" if precision == "fp32" else "legendre_bf16"
     with open(os.path.join(ROOT, "paper_2507_12144_amd", "csrc", src_file), "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -480,37 +484,45 @@ def main():
 
     # the same four transforms captured as one HIP graph and replayed (outside
     # the timed region above; reported beside it)
-    graph = plan.graph([("sht", u, y), ("isht", y, x2), ("isht_T", x2, gy), ("sht_T", gy, gx)])
-    for _ in range(3):
-        graph.launch()
-    torch.cuda.synchronize()
-    gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    gev[0].record(stream)
-    for i in range(args.steps):
-        graph.launch()
-        gev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    graph_ms = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps)])
-    graph.close()
+    graph_ms = None
+    if not args.profile_run:
+        graph = plan.graph([("sht", u, y), ("isht", y, x2), ("isht_T", x2, gy), ("sht_T", gy, gx)])
+        for _ in range(3):
+            graph.launch()
+        torch.cuda.synchronize()
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        gev[0].record(stream)
+        for i in range(args.steps):
+            graph.launch()
+            gev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        graph_ms = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps)])
+        graph.close()
 
     # roofline of the dominant kernel.  FP32: matrix-core bound, algorithmic
     # flops of the folded contraction.  bf16 forms: HBM bound, algorithmic
     # bytes = the folded table in its storage form + the dense spectrum.
     ana_ms, ana_n = kernels["legendre_analysis"]
     syn_ms, syn_n = kernels["legendre_synthesis"]
+    # a staged analysis is charged with its spectrum transpose
+    tr_ms, tr_n = kernels.get("transpose", (0.0, 0))
+    if tr_n:
+        ana_ms += tr_ms * ana_n / tr_n
     kind, tot, n = ("legendre_analysis", ana_ms, ana_n) if ana_ms >= syn_ms else ("legendre_synthesis", syn_ms, syn_n)
     flops = legendre_flops(nlat, L, M, F)
     nbytes = legendre_bytes(nlat, L, M, F, args.precision)
     avg_s = tot / max(n, 1) * 1e-3
     if args.precision == "fp32":
         achieved, peak = flops / avg_s / 1e12, PEAKS_TFLOPS["fp32"]
-        roofline = {"bound": "mfma", "kernel": kind, "achieved": round(achieved, 2), "peak": peak,
+        roofline = {"bound": "mfma", "kernel": kind + (" + spectrum transpose" if tr_n and kind == "legendre_analysis"
+                                                        else ""), "achieved": round(achieved, 2), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_flops_per_launch": flops}
         step_bound_ms = 4 * flops / (peak * 1e12) * 1e3
     else:
         achieved, peak = nbytes / avg_s / 1e9, HBM_PEAK_GBS
-        roofline = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": peak,
+        roofline = {"bound": "hbm", "kernel": kind + (" + spectrum transpose" if tr_n and kind == "legendre_analysis"
+                                                       else ""), "achieved": round(achieved, 1), "peak": peak,
                     "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": nbytes,
                     "mfma_tflops": round(flops * PRODUCTS[args.precision] / avg_s / 1e12, 2)}
@@ -519,6 +531,13 @@ def main():
     # the whole step against the sum of its dominant-kernel bounds (four
     # Legendre launches; the ring DFTs and everything else count as overhead)
     roofline["step_frac"] = round(step_bound_ms / p50, 4)
+    # the same fraction against the peaks measured on this GPU (a streaming
+    # copy, matrix-core loops)
+    peaks = None
+    if not args.profile_run:
+        peaks = P.measure_peaks()
+        roofline["peak_measured"] = peaks["fp32_mfma_TFs"] if args.precision == "fp32" else peaks["hbm_measured_GBs"]
+        roofline["frac_measured"] = round(achieved / roofline["peak_measured"], 4)
     prof = profiled_traffic(kind, args.precision)
     if prof is not None:
         roofline["traffic"] = prof["hbm_bytes_per_launch"]
@@ -588,9 +607,9 @@ def main():
         "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
         "step_ms": {"p10": round(float(np.percentile(step_ms, 10)), 4), "p50": round(p50, 4),
                     "p90": round(float(np.percentile(step_ms, 90)), 4)},
-        "graph_replay_ms": {"p10": round(float(np.percentile(graph_ms, 10)), 4),
-                            "p50": round(float(np.percentile(graph_ms, 50)), 4),
-                            "p90": round(float(np.percentile(graph_ms, 90)), 4)},
+        "graph_replay_ms": None if graph_ms is None else {
+            "p10": round(float(np.percentile(graph_ms, 10)), 4), "p50": round(float(np.percentile(graph_ms, 50)), 4),
+            "p90": round(float(np.percentile(graph_ms, 90)), 4)},
         "kernel_avg_us": per_kernel_us,
         "plan_build_s": round(plan_s, 3),
     }

@@ -233,7 +233,8 @@ sht_status sht_spatial_crps(sht_plan_t plan, const float* ens, const float* obs,
  *   sigma_{c,l} = F_0 e^{-k_T,c l (l+1) / 2},
  *   F_0 = sigma_c sqrt(2 pi (1 - phi_c^2) / sum_{0 < l < lmax} (2l+1) e^{-k_T,c l (l+1)}),
  * with eta standard normal per coefficient (Philox4x64-10 counter (flat
- * coefficient index, step, 0, 0), key (seed, 0); Box-Muller in float64):
+ * coefficient index, step, 0, 0), key (seed, 0); 53-bit uniforms, the
+ * Box-Muller functions in float32):
  * sigma_l (eta_re + i eta_im) for m >= 1, sqrt(2) sigma_l eta_re for m = 0,
  * degree 0 and l < m zero, so the stationary point-wise variance is
  * sigma_c^2.  sht_noise_create: kT, lambda, sigma are HOST arrays of
@@ -269,15 +270,26 @@ sht_status sht_isotropic_filter(sht_plan_t plan, const void* k, const void* in, 
  * summation order.  Timed as kind 5. */
 sht_status sht_isotropic_filter_grad(sht_plan_t plan, const void* g, const void* x, void* dk, void* hip_stream);
 
+/* Machine-peak microbenchmarks (diagnostics) for quoting roofline
+ * fractions against measured rather than datasheet peaks.  kind 0: HBM, a
+ * streaming copy between two library-allocated buffers of `size` bytes
+ * (multiple of 16), *result = bytes read + written per second; kind 1:
+ * FP32 matrix cores (v_mfma_f32_16x16x4_f32), kind 2: BF16 matrix cores
+ * (v_mfma_f32_16x16x32_bf16), `size` iterations of eight independent
+ * accumulators in 2048 four-wave workgroups, *result = flop/s.  One timed
+ * launch after a warm-up; synchronises hip_stream. */
+sht_status sht_measure_peak(int kind, size_t size, double* result, void* hip_stream);
+
 /* Kernel timing (diagnostics).  With enable != 0 every later call on the
  * plan records a pair of HIP events on the call's stream around each kernel
  * it launches.  sht_plan_timing_read waits for the recorded events, adds the
  * elapsed milliseconds and launch counts per kernel kind into ms[i] and
  * counts[i] for i < nkinds (kinds: 0 ring DFT forward, 1 ring DFT inverse,
  * 2 Legendre analysis, 3 Legendre synthesis, 4 zero fill, 5 channel mix,
- * 6 scores and spectra, 7 noise),
+ * 6 scores and spectra, 7 noise, 8 spectrum transpose of the staged
+ * analysis),
  * then forgets them.  Host arrays; nkinds <= SHT_TIMING_KINDS. */
-#define SHT_TIMING_KINDS 8
+#define SHT_TIMING_KINDS 9
 sht_status sht_plan_timing(sht_plan_t plan, int enable);
 sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds);
 
@@ -306,8 +318,10 @@ sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream);
 sht_status sht_graph_destroy(sht_graph_t graph);
 
 /* Autotuner.  The work decomposition of a plan has free parameters that do
- * not change any result bit: the field groups (of 8 fields) per workgroup
- * of the float32 Legendre kernels (2, 3 or 4; the bf16 forms always take 2),
+ * not change any result bit: whether the analysis output is staged in
+ * order-major tiles and transposed (see sht_plan_set_schedule), the field
+ * groups (of 8 fields) per workgroup of the float32 Legendre kernels (2, 3
+ * or 4; the bf16 forms always take 2),
  * the orders per scheduling chunk of the Legendre work list (4, 8, 16, 32)
  * and how chunks are dealt to the 8 XCDs (largest-first to the least-loaded
  * XCD, or round robin).  sht_plan_tune times one SHT -> ISHT -> ISHT^T ->
@@ -326,11 +340,14 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
 
 /* Set the schedule explicitly (chunk: orders per chunk, 1..64; policy: 0
  * least-loaded XCD, 1 round robin; ncb: field groups per workgroup of the
- * float32 kernels, 2..4, ignored by the bf16 forms), or read the one in
- * use.  Results do not change.  SHT_ERR_INVALID_ARG while graphs of the plan
- * exist (they hold the old work list). */
-sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb);
-sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb);
+ * float32 kernels, 2..4, ignored by the bf16 forms; staged: 1 = the
+ * analysis writes order-major tiles to plan-owned staging and a transpose
+ * kernel writes the spectrum in full lines, 0 = the analysis stores into
+ * the spectrum directly), or read the one in use.  Results do not change.
+ * SHT_ERR_INVALID_ARG while graphs of the plan exist (they hold the old work
+ * list). */
+sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb, int staged);
+sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb, int* staged);
 
 const char* sht_status_string(sht_status s);
 const char* sht_last_error(void);

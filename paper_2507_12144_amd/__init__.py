@@ -244,15 +244,17 @@ class Plan:
         _lib.check(_lib.load().sht_plan_tune(self._h, path, ctypes.byref(chosen), ctypes.byref(ms)))
         return chosen.value, ms.value
 
-    def set_schedule(self, chunk=8, policy=0, ncb=2):
+    def set_schedule(self, chunk=8, policy=0, ncb=2, staged=1):
         """Set the work schedule explicitly (results do not change)."""
-        _lib.check(_lib.load().sht_plan_set_schedule(self._h, int(chunk), int(policy), int(ncb)))
+        _lib.check(_lib.load().sht_plan_set_schedule(self._h, int(chunk), int(policy), int(ncb), int(staged)))
 
     def schedule(self):
-        """(orders per chunk, XCD policy, field groups per workgroup) in use."""
-        c, p, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _lib.check(_lib.load().sht_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(n)))
-        return c.value, p.value, n.value
+        """(orders per chunk, XCD policy, field groups per workgroup, staged
+        analysis output) in use."""
+        c, p, n, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(_lib.load().sht_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(n),
+                                                     ctypes.byref(st)))
+        return c.value, p.value, n.value, st.value
 
     def graph(self, ops):
         """Capture a sequence [(op, input, output), ...] (op in "sht", "isht",
@@ -284,6 +286,34 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def measure_peaks(copy_bytes=1 << 30, iters=4096):
+    """Measured machine peaks on the current GPU: HBM copy GB/s (read +
+    written; the library's copy kernel and torch's device copy, the larger
+    taken as the measured HBM peak), FP32 and BF16 matrix-core TFLOP/s
+    (sht_measure_peak)."""
+    lib = _lib.load()
+    st = _stream_ptr(torch.cuda.current_device())
+    out = {}
+    for name, kind, size, scale in (("hbm_copy_GBs", 0, copy_bytes, 1e9), ("fp32_mfma_TFs", 1, iters, 1e12),
+                                    ("bf16_mfma_TFs", 2, iters, 1e12)):
+        r = ctypes.c_double()
+        _lib.check(lib.sht_measure_peak(kind, size, ctypes.byref(r), st))
+        out[name] = round(r.value / scale, 1)
+    # torch's own device-to-device copy of the same size, for comparison
+    a = torch.empty(copy_bytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    out["torch_copy_GBs"] = round(2 * copy_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    out["hbm_measured_GBs"] = max(out["hbm_copy_GBs"], out["torch_copy_GBs"])
+    del a, b
+    return out
 
 
 class SHT(torch.autograd.Function):

@@ -16,7 +16,7 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x2": 2, "bf16x3": 3}
 EXPORTS = ["sht_plan", "sht_plan_destroy", "sht_plan_segment", "sht_plan_sizes", "sht_plan_grid",
            "sht_forward", "isht_forward", "sht_backward", "isht_backward", "sht_channel_mix",
            "sht_channel_mix_weight_grad", "sht_isotropic_filter", "sht_isotropic_filter_grad", "sht_graph_create", "sht_graph_launch", "sht_graph_destroy", "sht_plan_tune",
-           "sht_plan_set_schedule", "sht_plan_get_schedule",
+           "sht_plan_set_schedule", "sht_plan_get_schedule", "sht_measure_peak",
            "sht_plan_timing", "sht_plan_timing_read", "sht_psd", "sht_zonal_psd", "sht_spectral_crps",
            "sht_spectral_crps_noalloc", "sht_spatial_crps", "sht_noise_create", "sht_noise_step", "sht_noise_set_step", "sht_noise_destroy",
            "sht_status_string", "sht_last_error"]
@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan", "sht_plan_destroy", "sht_plan_segment", "sht_plan_sizes",
 OPS = {"sht": 0, "isht": 1, "sht_T": 2, "isht_T": 3}
 
 TIMING_KINDS = ["dft_forward", "dft_inverse", "legendre_analysis", "legendre_synthesis", "zero_fill",
-                "channel_mix", "scores", "noise"]
+                "channel_mix", "scores", "noise", "transpose"]
 
 
 class ShtDesc(ctypes.Structure):
@@ -64,9 +64,10 @@ def load():
     lib.sht_isotropic_filter.argtypes = [vp, vp, vp, vp, ip, vp]
     lib.sht_isotropic_filter_grad.argtypes = [vp, vp, vp, vp, vp]
     lib.sht_plan_timing.argtypes = [vp, ip]
-    lib.sht_plan_set_schedule.argtypes = [vp, ip, ip, ip]
+    lib.sht_plan_set_schedule.argtypes = [vp, ip, ip, ip, ip]
+    lib.sht_measure_peak.argtypes = [ip, sz, ctypes.POINTER(ctypes.c_double), vp]
     ipp = ctypes.POINTER(ctypes.c_int)
-    lib.sht_plan_get_schedule.argtypes = [vp, ipp, ipp, ipp]
+    lib.sht_plan_get_schedule.argtypes = [vp, ipp, ipp, ipp, ipp]
     lib.sht_plan_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), ip]
     lib.sht_psd.argtypes = [vp, vp, vp, vp]
     lib.sht_zonal_psd.argtypes = [vp, vp, vp, vp]

@@ -102,6 +102,8 @@ struct Segment {
   void* tab_syn = nullptr;     // Legendre table, synthesis fragment order
   int64_t* tab_off = nullptr;  // [mmax]
   float* work = nullptr;
+  float* ystage = nullptr;     // staged analysis output (order-major tiles)
+  int64_t* ystage_off = nullptr;  // [mmax]
 };
 
 sht_status validate_desc(const sht_desc& d, int i) {
@@ -151,8 +153,9 @@ struct sht_plan_s {
   int2* bwork = nullptr;
   sht::BatchArgs batch{};
   // schedule (sht_plan_tune): orders per chunk, XCD dealing policy, field
-  // groups per workgroup of the float32 Legendre kernels
-  int tune_chunk = 8, tune_policy = 0, tune_ncb = 2;
+  // groups per workgroup of the float32 Legendre kernels, staged analysis
+  // output (order-major tiles + spectrum transpose) or direct stores
+  int tune_chunk = 8, tune_policy = 0, tune_ncb = 2, tune_staged = 1;
   int graphs = 0;  // live sht_graph_t objects of this plan
   int noises = 0;  // live sht_noise_t objects of this plan
 };
@@ -177,7 +180,7 @@ namespace {
 
 void free_segment(Segment& s) {
   void* ptrs[] = {s.x, s.s, s.w, s.scale_sht, s.scale_one, s.scale_zonal, s.ring_w, s.partial, s.tw, s.tab_ana,
-                  s.tab_syn, s.tab_off, s.work};
+                  s.tab_syn, s.tab_off, s.work, s.ystage, s.ystage_off};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   s = Segment{};
@@ -313,6 +316,20 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
     if (e != hipSuccess) return hip_fail(e, "Legendre table kernel");
   }
 
+  // staging of the analysis output: per order m, parity p and field group
+  // g, nb(m) = ceil(ceil((lmax - m) / 2) / 16) tiles of 16 x 16 floats
+  {
+    std::vector<int64_t> off(d.mmax);
+    int64_t n = 0;
+    for (int m = 0; m < d.mmax; ++m) {
+      off[m] = n;
+      n += 2LL * g.groups * ((((d.lmax - m + 1) >> 1) + 15) / 16) * 256;
+    }
+    if ((rc = upload(&S.ystage_off, off, st, "staging offsets")) != SHT_OK) return rc;
+    e = dev_alloc(reinterpret_cast<void**>(&S.ystage), static_cast<size_t>(n) * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "analysis staging allocation");
+  }
+
   // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
   const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.groups * g.kpad * 16 * sizeof(float);
   e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
@@ -374,6 +391,7 @@ std::vector<int2> deal_chunks(std::vector<WorkChunk> chunks, int policy, size_t*
 sht_status apply_schedule(sht_plan_s* p) {
   const int ncb = p->storage == Storage::F32 ? p->tune_ncb : kBatchNcb;
   p->batch.ncb = ncb;
+  p->batch.staged = p->tune_staged;
   std::vector<WorkChunk> chunks;
   for (size_t i = 0; i < p->segs.size(); ++i)
     add_chunks(&chunks, p->segs[i].d, (p->segs[i].g.groups + ncb - 1) / ncb, static_cast<int>(i) << 16,
@@ -395,7 +413,7 @@ sht_status apply_schedule(sht_plan_s* p) {
 // segments are built.
 sht_status build_batch(sht_plan_s* p) {
   std::vector<SegDev> h(p->segs.size());
-  int items = 0;
+  int items = 0, tiles = 0;
   size_t lds = 0;
   for (size_t i = 0; i < p->segs.size(); ++i) {
     const Segment& S = p->segs[i];
@@ -413,6 +431,10 @@ sht_status build_batch(sht_plan_s* p) {
     d.spec_off = static_cast<long long>(S.spec_off);
     d.dft_begin = items;
     d.dft_items = 2 * S.g.groups * S.g.nk;
+    d.ystage = S.ystage;
+    d.ystage_off = S.ystage_off;
+    d.tr_begin = tiles;
+    tiles += spectrum_transpose_tiles(S.g);
     d.nstages = S.dp.nstages;
     for (int r = 0; r < kMaxRadices; ++r) d.radix[r] = S.dp.radix[r];
     items += d.dft_items;
@@ -423,6 +445,7 @@ sht_status build_batch(sht_plan_s* p) {
   p->batch.segs = p->d_segs;
   p->batch.nseg = static_cast<int>(h.size());
   p->batch.dft_total = items;
+  p->batch.tr_total = tiles;
   p->batch.dft_lds = lds;
   hipError_t e = prepare_dft_kernels(lds);
   if (e != hipSuccess) return hip_fail(e, "ring DFT kernel attributes");
@@ -433,7 +456,10 @@ hipStream_t pick_stream(const sht_plan_s* p, void* s) {
   return s ? static_cast<hipStream_t>(s) : p->stream;
 }
 
-enum Kind { K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5, K_SCORE = 6, K_NOISE = 7 };
+enum Kind {
+  K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5, K_SCORE = 6, K_NOISE = 7,
+  K_TRANSPOSE = 8
+};
 
 hipEvent_t take_event(sht_plan_s* p) {
   if (!p->event_pool.empty()) {
@@ -495,6 +521,8 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
       e = timed(plan, K_DFT_FWD, st,
                 [&] { return launch_dft_forward_batched(B, static_cast<const float*>(in), fwd, st); });
       if (e == hipSuccess) e = timed(plan, K_LEG_ANA, st, [&] { return legendre(true, nullptr, out, fwd ? 1.f : 2.f); });
+      if (e == hipSuccess && B.staged)
+        e = timed(plan, K_TRANSPOSE, st, [&] { return launch_spectrum_transpose(B, static_cast<float2*>(out), st); });
       break;
     }
     case Op::ISHT:
@@ -538,6 +566,12 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
   if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
   p->prec = prec;
   p->storage = storage_of(prec);
+  // Staged analysis output by default only for the split bf16 forms: there
+  // the scattered spectrum stores cost more than the transpose that replaces
+  // them (measured at 721 x 1440, 72 fields: 387 -> 267 + 107 us); for
+  // float32 and plain bf16 the direct stores are a little cheaper.  The
+  // tuner measures both.
+  p->tune_staged = (p->storage == Storage::BF16X2 || p->storage == Storage::BF16X3) ? 1 : 0;
   p->stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
@@ -779,17 +813,24 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   // per chunk x XCD dealing.  The default comes first: every other one must
   // reproduce its outputs bit for bit.
   struct Cand {
-    int chunk, policy, ncb;
+    int chunk, policy, ncb, staged;
   };
-  std::vector<Cand> cands = {{8, 0, 2}, {4, 0, 2}, {16, 0, 2}, {32, 0, 2}, {8, 1, 2}, {16, 1, 2}};
-  if (plan->storage == Storage::F32)
-    for (int ncb : {3, 4})
-      for (Cand c : {Cand{8, 0, ncb}, Cand{4, 0, ncb}, Cand{16, 0, ncb}, Cand{8, 1, ncb}})
-        if (legendre_ncb_supported(ncb)) cands.push_back(c);
+  std::vector<Cand> cands;
+  for (int staged : {1, 0}) {
+    for (Cand c : {Cand{8, 0, 2, staged}, Cand{4, 0, 2, staged}, Cand{16, 0, 2, staged}, Cand{32, 0, 2, staged},
+                   Cand{8, 1, 2, staged}, Cand{16, 1, 2, staged}})
+      cands.push_back(c);
+    if (plan->storage == Storage::F32)
+      for (int ncb : {3, 4})
+        for (Cand c : {Cand{8, 0, ncb, staged}, Cand{4, 0, ncb, staged}, Cand{16, 0, ncb, staged},
+                       Cand{8, 1, ncb, staged}})
+          if (legendre_ncb_supported(ncb)) cands.push_back(c);
+  }
   auto apply = [&](const Cand& c) {
     plan->tune_chunk = c.chunk;
     plan->tune_policy = c.policy;
     plan->tune_ncb = c.ncb;
+    plan->tune_staged = c.staged;
     return apply_schedule(plan);
   };
   // cache key: arch | descriptors | precision
@@ -803,7 +844,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
              static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
     key += buf;
   }
-  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v2";
+  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v3";
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -870,7 +911,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   sht_status rc = SHT_OK;
   int best = 0;
   float best_t = 0.f;
-  const Cand saved{plan->tune_chunk, plan->tune_policy, plan->tune_ncb};
+  const Cand saved{plan->tune_chunk, plan->tune_policy, plan->tune_ncb, plan->tune_staged};
   for (size_t ci = 0; ci < cands.size() && rc == SHT_OK; ++ci) {
     rc = apply(cands[ci]);
     if (rc != SHT_OK) break;
@@ -927,6 +968,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
     plan->tune_chunk = saved.chunk;
     plan->tune_policy = saved.policy;
     plan->tune_ncb = saved.ncb;
+    plan->tune_staged = saved.staged;
     (void)apply_schedule(plan);
     return rc;
   }
@@ -941,23 +983,36 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
   return SHT_OK;
 }
 
-sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb) {
+sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb, int staged) {
   if (!plan) return fail(SHT_ERR_INVALID_ARG, "plan is NULL");
   if (plan->graphs > 0) return fail(SHT_ERR_INVALID_ARG, "destroy the plan's graphs before changing its schedule");
   if (chunk < 1 || chunk > 64) return fail(SHT_ERR_INVALID_ARG, "chunk must be in [1, 64]");
   if (policy != 0 && policy != 1) return fail(SHT_ERR_INVALID_ARG, "policy must be 0 or 1");
   if (!legendre_ncb_supported(ncb)) return fail(SHT_ERR_INVALID_ARG, "ncb must be 2, 3 or 4");
+  if (staged != 0 && staged != 1) return fail(SHT_ERR_INVALID_ARG, "staged must be 0 or 1");
   plan->tune_chunk = chunk;
   plan->tune_policy = policy;
   plan->tune_ncb = ncb;
+  plan->tune_staged = staged;
   return apply_schedule(plan);
 }
 
-sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb) {
-  if (!plan || !chunk || !policy || !ncb) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
+sht_status sht_plan_get_schedule(sht_plan_t plan, int* chunk, int* policy, int* ncb, int* staged) {
+  if (!plan || !chunk || !policy || !ncb || !staged) return fail(SHT_ERR_INVALID_ARG, "NULL argument");
   *chunk = plan->tune_chunk;
   *policy = plan->tune_policy;
   *ncb = plan->batch.ncb;
+  *staged = plan->batch.staged;
+  return SHT_OK;
+}
+
+sht_status sht_measure_peak(int kind, size_t size, double* result, void* hip_stream) {
+  if (!result) return fail(SHT_ERR_INVALID_ARG, "result is NULL");
+  if (kind < 0 || kind > 2) return fail(SHT_ERR_INVALID_ARG, "kind must be 0, 1 or 2");
+  if (size < 1 || (kind == 0 && (size % 16 != 0 || size > (size_t(1) << 36))) || (kind > 0 && size > (1u << 24)))
+    return fail(SHT_ERR_INVALID_ARG, "size out of range");
+  hipError_t e = measure_peak(kind, size, result, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "peak microbenchmark");
   return SHT_OK;
 }
 

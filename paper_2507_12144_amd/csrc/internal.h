@@ -66,6 +66,9 @@ struct SegDev {
   long long spec_off;      // first complex of the segment in spectral buffers
   int dft_begin;           // first DFT item of the segment (plan-wide numbering)
   int dft_items;           // 2 * groups * nk
+  float* ystage;           // staged analysis output Y'[m][p][g][ib][16][16]
+  const int64_t* ystage_off;  // [mmax] first float of order m in ystage
+  int tr_begin;            // first spectrum-transpose tile (plan-wide numbering)
   int nstages;             // DFT radix plan (generic widths)
   int radix[kMaxRadices];
 };
@@ -79,6 +82,8 @@ struct BatchArgs {
   int dft_total;           // DFT items of all segments
   size_t dft_lds;          // dynamic LDS of the batched DFT kernels
   int ncb;                 // field groups per column chunk (workgroup) of the Legendre kernels
+  int staged;              // analysis writes tiles to ystage, then the spectrum transpose runs
+  int tr_total;            // spectrum-transpose tiles of all segments
 };
 // Field groups per column chunk of the bf16 Legendre kernels (the float32
 // kernels take BatchArgs::ncb, see legendre_ncb_supported).
@@ -120,6 +125,13 @@ hipError_t launch_legendre_analysis_bf16_batched(const BatchArgs& b, int planes,
                                                  hipStream_t st);
 hipError_t launch_legendre_synthesis_bf16_batched(const BatchArgs& b, int planes, const float2* y, hipStream_t st);
 
+// ---- transpose.hip -------------------------------------------------------
+// Tiles of the spectrum transpose for one segment, and the transpose of every
+// segment's staged analysis output Y' into the spectral buffer y (writes the
+// whole spectrum, zeros for l < m included).
+int spectrum_transpose_tiles(const SegGeom& g);
+hipError_t launch_spectrum_transpose(const BatchArgs& b, float2* y, hipStream_t st);
+
 // ---- scores.hip ----------------------------------------------------------
 // Angular PSD (App. F.7, eq. psd): out[f][l] = sum_{m <= min(l, mmax-1)} c_m |y[f][l][m]|^2.
 hipError_t launch_psd(const float2* y, long long F, int lmax, int mmax, float* out, hipStream_t st);
@@ -148,6 +160,11 @@ hipError_t launch_crps(const CrpsShape& s, const float* ens, const float* obs, c
 // stationary start.
 hipError_t launch_noise_step(int batch, int channels, int lmax, int mmax, const double* sigma_l, const double* phi,
                              unsigned long long seed, unsigned long long step, float2* y, hipStream_t st);
+
+// ---- peak.hip ------------------------------------------------------------
+// kind 0: HBM copy of `size` bytes (result bytes/s, read + written);
+// kind 1 / 2: FP32 / BF16 matrix-core loop of `size` iterations (flop/s).
+hipError_t measure_peak(int kind, size_t size, double* result, hipStream_t st);
 
 // ---- mix.hip -------------------------------------------------------------
 // dW[l][c'][c] = sum_{b, m <= min(l, mmax-1)} g[b][c'][l][m] conj(x[b][c][l][m])

@@ -94,7 +94,8 @@ __device__ __forceinline__ void issue_stage(v4f* B, const float* __restrict__ ta
 // lane group lk, piece t of the row block and component q.
 template <int NCB, int KS>
 __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, const float* __restrict__ W,
-                                              float2* __restrict__ y, float c_rest, v4f* b0, v4f* b1, v4f* b2) {
+                                              float2* __restrict__ y, float c_rest, int staged, v4f* b0, v4f* b1,
+                                              v4f* b2) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, NTH = S::NTH, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
@@ -185,13 +186,23 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[kb + 4 * t + 3], acc, 0, 0, 0);
           }
           if constexpr (part == PARTS - 1) {
-            if (fok) {
+            if (staged) {
+              // the 16 x 16 tile, contiguous, into the order-major staging
+              // buffer (rows past the parity's last degree hold zeros)
+              float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dst[(4 * lk + r) * 16 + li] = acc[r] * ms;
+            } else {
+              // lane pairs (li, li ^ 1) hold re and im of one field: the
+              // even lane stores both (8 bytes)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
+                const float other = __shfl_xor(acc[r], 1, 64);
                 const int i = 16 * ib + 4 * lk + r;
-                if (i < np) {
+                if (fok && (li & 1) == 0 && i < np) {
                   const int l = m + p + 2 * i;
-                  yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = acc[r] * ms;
+                  *reinterpret_cast<float2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
+                      make_float2(acc[r] * ms, other * ms);
                 }
               }
             }
@@ -206,8 +217,9 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
   }
   // Zeros of the spectrum (entries l < m'): this workgroup writes those of
   // degree l = m for its fields, y[f][m][m+1 .. mmax-1], one contiguous run
-  // per field, instead of the scattered column y[f][0 .. m-1][m].
-  if (m < g.lmax) {
+  // per field, instead of the scattered column y[f][0 .. m-1][m].  (Staged:
+  // the transpose writes them.)
+  if (!staged && m < g.lmax) {
     const int fbeg = 8 * NCB * c;
     const int fend = min(g.F, fbeg + 8 * NCB);
     const int run = g.mmax - 1 - m;
@@ -347,7 +359,8 @@ static_assert(2 * Stages<2, 64>::SC <= kMaxStagePieces && 2 * Stages<2, 48>::SC 
 // from the reads of another) and sized for the largest geometry.
 template <int NCB>
 __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void analysis_batched(
-    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest) {
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest,
+    int staged) {
   __shared__ v4f b0[kMaxStagePieces * 64], b1[kMaxStagePieces * 64], b2[kMaxStagePieces * 64];
   const int2 wk = take_work(work, per);
   if (wk.x < 0) return;
@@ -355,11 +368,11 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const int m = wk.x, c = wk.y & 0xffff;
   float2* ys = y + sd.spec_off;
   switch (sd.g.kpad) {
-    case 64: analysis_body<NCB, 16>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
-    case 128: analysis_body<NCB, 32>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
-    case 192: analysis_body<NCB, 48>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
-    case 256: analysis_body<NCB, 64>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
-    default: analysis_body<NCB, 96>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2); break;
+    case 64: analysis_body<NCB, 16>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
+    case 128: analysis_body<NCB, 32>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
+    case 192: analysis_body<NCB, 48>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
+    case 256: analysis_body<NCB, 64>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
+    default: analysis_body<NCB, 96>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
   }
 }
 
@@ -389,7 +402,7 @@ hipError_t launch_ncb(bool analysis, const BatchArgs& b, const float2* in, float
                       hipStream_t st) {
   const dim3 grid(static_cast<unsigned>(8 * b.work_per)), block(128 * NCB);
   if (analysis)
-    hipLaunchKernelGGL(analysis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, out, c_rest);
+    hipLaunchKernelGGL(analysis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, out, c_rest, b.staged);
   else
     hipLaunchKernelGGL(synthesis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, in);
   return hipGetLastError();

@@ -167,7 +167,7 @@ constexpr int s_behind(int s) {
 // S or A (each wave its own four pieces); stage XS + s is table stage s.
 template <int KS, int NP, int NBUF>
 __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, float2* __restrict__ y, float c_rest,
-                                              v4f* ring) {
+                                              int staged, v4f* ring) {
   constexpr int T8 = KS / 8;  // steps per 16-row block
   using G = Geo<T8, NP, KS / 4, NBUF>;
   constexpr int SC = G::SC, SS = G::SS, LPW = G::LPW, PARTS = G::PARTS;
@@ -245,13 +245,23 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
             products<NP, ND>(av, xs[part * SS + s], main, corr);
           }
           if constexpr (part == PARTS - 1) {
-            if (fok) {
+            if (staged) {
+              // the 16 x 16 tile, contiguous, into the order-major staging buffer
+              float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dst[(4 * lk + r) * 16 + li] = (main[r] + corr[r]) * ms;
+            } else {
+              // lane pairs (li, li ^ 1) hold re and im of one field: the
+              // even lane stores both (8 bytes)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
+                const float v = main[r] + corr[r];
+                const float other = __shfl_xor(v, 1, 64);
                 const int i = 16 * ib + 4 * lk + r;
-                if (i < np) {
+                if (fok && (li & 1) == 0 && i < np) {
                   const int l = m + p + 2 * i;
-                  yf[((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2 + (li & 1)] = (main[r] + corr[r]) * ms;
+                  *reinterpret_cast<float2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
+                      make_float2(v * ms, other * ms);
                 }
               }
             }
@@ -266,8 +276,9 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
     __builtin_amdgcn_s_waitcnt(vm_wait(0));
   }
   // zeros of the spectrum: degree l = m, orders m+1 .. mmax-1 of this
-  // chunk's fields (contiguous runs; the orders together cover every l < m')
-  if (m < g.lmax) {
+  // chunk's fields (contiguous runs; the orders together cover every l < m';
+  // staged: the transpose writes them)
+  if (!staged && m < g.lmax) {
     const int fbeg = 16 * c;
     const int fend = min(g.F, fbeg + 16);
     const int run = g.mmax - 1 - m;
@@ -391,7 +402,8 @@ constexpr int kSynBuffers = 4;
 // Batched kernels of one plane count (items {m, (segment << 16) | chunk}).
 template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void analysis_batched(
-    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest) {
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, float2* __restrict__ y, float c_rest,
+    int staged) {
   __shared__ v4f ring[kRingBuffers * 16 * 64];
   const int2 wk = take_work(work, per);
   if (wk.x < 0) return;
@@ -400,11 +412,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   float2* ys = y + sd.spec_off;
   constexpr int R = kRingBuffers;
   switch (sd.g.kpad) {
-    case 64: analysis_body<16, NP, R>(sd, m, c, ys, c_rest, ring); break;
-    case 128: analysis_body<32, NP, R>(sd, m, c, ys, c_rest, ring); break;
-    case 192: analysis_body<48, NP, R>(sd, m, c, ys, c_rest, ring); break;
-    case 256: analysis_body<64, NP, R>(sd, m, c, ys, c_rest, ring); break;
-    default: analysis_body<96, NP, R>(sd, m, c, ys, c_rest, ring); break;
+    case 64: analysis_body<16, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
+    case 128: analysis_body<32, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
+    case 192: analysis_body<48, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
+    case 256: analysis_body<64, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
+    default: analysis_body<96, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
   }
 }
 
@@ -438,7 +450,7 @@ hipError_t launch_batched(bool analysis, const BatchArgs& b, const void* in, voi
   const dim3 grid(static_cast<unsigned>(8 * b.work_per));
   if (analysis)
     hipLaunchKernelGGL(analysis_batched<NP>, grid, dim3(256), 0, st, b.segs, b.work, b.work_per,
-                       static_cast<float2*>(out), c_rest);
+                       static_cast<float2*>(out), c_rest, b.staged);
   else
     hipLaunchKernelGGL(synthesis_batched<NP>, grid, dim3(256), 0, st, b.segs, b.work, b.work_per,
                        static_cast<const float2*>(in));

@@ -708,22 +708,43 @@ def test_tune_parity_and_cache(pkg, tmp_path, prec):
                                    (181, 360, 180, 180, 0, 1, 37)],
                          ids=lambda s: f"{s[0]}x{s[1]}_F{s[5] * s[6]}")
 def test_field_groups_per_workgroup_are_bitwise_equal(pkg, shape):
-    """The float32 kernels with 2, 3 and 4 field groups per workgroup (a
-    tuning choice) give the same bits for all four transforms, also with a
-    ragged last column chunk."""
-    _say("ncb schedules", shape)
+    """The float32 kernels with 2, 3 and 4 field groups per workgroup and
+    with the analysis output staged (order-major tiles + spectrum transpose)
+    or stored directly (tuning choices) give the same bits for all four
+    transforms, also with a ragged last column chunk."""
+    _say("schedules", shape)
     nlat, nlon, L, M, grid, B, C = shape
     plan = _plan(pkg, *shape)
     u = _to_dev(synth.grid_normal(31, (B, C, nlat, nlon)), torch.float32)
     a = _to_dev(synth.coefficients(32, B, C, L, M), torch.complex64)
     ref = None
-    for ncb in (2, 3, 4):
-        plan.set_schedule(8, 0, ncb)
-        assert plan.schedule() == (8, 0, ncb)
-        outs = [plan.sht(u), plan.isht(a), plan.sht_T(a), plan.isht_T(u)]
-        if ref is None:
-            ref = outs
-        else:
-            for o, r in zip(outs, ref):
-                assert torch.equal(o, r), ncb
+    for staged in (0, 1):
+        for ncb in (2, 3, 4):
+            plan.set_schedule(8, 0, ncb, staged)
+            assert plan.schedule() == (8, 0, ncb, staged)
+            outs = [plan.sht(u), plan.isht(a), plan.sht_T(a), plan.isht_T(u)]
+            if ref is None:
+                ref = outs
+            else:
+                for o, r in zip(outs, ref):
+                    assert torch.equal(o, r), (ncb, staged)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x2", "bf16x3"])
+def test_staged_analysis_bitwise_equal_bf16_forms(pkg, prec):
+    """Staged and direct analysis output of the bf16 forms, bitwise, on a
+    multi-segment plan (every ring padding, odd mmax, mmax < lmax)."""
+    shapes = [(33, 64, 17, 17, 0, 1, 3), (65, 128, 64, 41, 0, 2, 3), (181, 360, 180, 180, 0, 1, 5),
+              (721, 1440, 720, 720, 0, 1, 2)]
+    _say("staged bf16", prec)
+    plan = _multi_plan(pkg, shapes, prec)
+    u_h, _, _ = _batched_io(pkg, plan, shapes, seed=33)
+    u = _to_dev(u_h, torch.float32)
+    mask = _segment_mask(plan, shapes, True)
+    outs = []
+    for staged in (0, 1):
+        plan.set_schedule(8, 0, 2, staged)
+        outs.append((plan.sht(u).cpu().numpy()[mask], plan.isht_T(u).cpu().numpy()[mask]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     plan.close()
