@@ -504,25 +504,29 @@ def main():
     # bytes = the folded table in its storage form + the dense spectrum.
     ana_ms, ana_n = kernels["legendre_analysis"]
     syn_ms, syn_n = kernels["legendre_synthesis"]
-    # a staged analysis is charged with its spectrum transpose
+    # a staged analysis is charged with its spectrum transpose, a staged
+    # synthesis input with its staging kernel
     tr_ms, tr_n = kernels.get("transpose", (0.0, 0))
     if tr_n:
         ana_ms += tr_ms * ana_n / tr_n
+    sg_ms, sg_n = kernels.get("stage", (0.0, 0))
+    if sg_n:
+        syn_ms += sg_ms * syn_n / sg_n
     kind, tot, n = ("legendre_analysis", ana_ms, ana_n) if ana_ms >= syn_ms else ("legendre_synthesis", syn_ms, syn_n)
+    extra = (" + spectrum transpose" if tr_n and kind == "legendre_analysis" else
+             " + input staging" if sg_n and kind == "legendre_synthesis" else "")
     flops = legendre_flops(nlat, L, M, F)
     nbytes = legendre_bytes(nlat, L, M, F, args.precision)
     avg_s = tot / max(n, 1) * 1e-3
     if args.precision == "fp32":
         achieved, peak = flops / avg_s / 1e12, PEAKS_TFLOPS["fp32"]
-        roofline = {"bound": "mfma", "kernel": kind + (" + spectrum transpose" if tr_n and kind == "legendre_analysis"
-                                                        else ""), "achieved": round(achieved, 2), "peak": peak,
+        roofline = {"bound": "mfma", "kernel": kind + extra, "achieved": round(achieved, 2), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_flops_per_launch": flops}
         step_bound_ms = 4 * flops / (peak * 1e12) * 1e3
     else:
         achieved, peak = nbytes / avg_s / 1e9, HBM_PEAK_GBS
-        roofline = {"bound": "hbm", "kernel": kind + (" + spectrum transpose" if tr_n and kind == "legendre_analysis"
-                                                       else ""), "achieved": round(achieved, 1), "peak": peak,
+        roofline = {"bound": "hbm", "kernel": kind + extra, "achieved": round(achieved, 1), "peak": peak,
                     "unit": "GB/s", "frac": round(achieved / peak, 4), "traffic": None,
                     "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": nbytes,
                     "mfma_tflops": round(flops * PRODUCTS[args.precision] / avg_s / 1e12, 2)}

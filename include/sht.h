@@ -102,7 +102,11 @@ typedef struct sht_plan_s* sht_plan_t;
  * as the default stream of later calls (NULL: the null stream).
  * *out is set to NULL on failure; a failed build frees everything it had
  * allocated.  Test hook: with SHT_TEST_FAIL_ALLOC=n in the environment the
- * n-th device allocation of the call fails (SHT_ERR_OUT_OF_MEMORY). */
+ * n-th device allocation of the call fails (SHT_ERR_OUT_OF_MEMORY).
+ * Environment: SHT_AUTOTUNE=1 runs sht_plan_tune on the new plan (cache
+ * file from SHT_TUNE_CACHE, if set); SHT_DEBUG=1 makes every call
+ * synchronise its stream after each kernel it launches (outside stream
+ * capture), so a kernel fault is reported as SHT_ERR_HIP by that call. */
 sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc,
                     sht_precision prec, void* hip_stream);
 
@@ -287,9 +291,9 @@ sht_status sht_measure_peak(int kind, size_t size, double* result, void* hip_str
  * counts[i] for i < nkinds (kinds: 0 ring DFT forward, 1 ring DFT inverse,
  * 2 Legendre analysis, 3 Legendre synthesis, 4 zero fill, 5 channel mix,
  * 6 scores and spectra, 7 noise, 8 spectrum transpose of the staged
- * analysis),
- * then forgets them.  Host arrays; nkinds <= SHT_TIMING_KINDS. */
-#define SHT_TIMING_KINDS 9
+ * analysis output, 9 staging of the synthesis input), then forgets them.
+ * Host arrays; nkinds <= SHT_TIMING_KINDS. */
+#define SHT_TIMING_KINDS 10
 sht_status sht_plan_timing(sht_plan_t plan, int enable);
 sht_status sht_plan_timing_read(sht_plan_t plan, double* ms, long long* counts, int nkinds);
 
@@ -340,10 +344,12 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
 
 /* Set the schedule explicitly (chunk: orders per chunk, 1..64; policy: 0
  * least-loaded XCD, 1 round robin; ncb: field groups per workgroup of the
- * float32 kernels, 2..4, ignored by the bf16 forms; staged: 1 = the
- * analysis writes order-major tiles to plan-owned staging and a transpose
- * kernel writes the spectrum in full lines, 0 = the analysis stores into
- * the spectrum directly), or read the one in use.  Results do not change.
+ * float32 kernels, 2..4, ignored by the bf16 forms; staged, a bit mask:
+ * bit 0 = the analysis writes order-major tiles to plan-owned staging and a
+ * transpose kernel writes the spectrum in full lines (else the analysis
+ * stores into the spectrum directly), bit 1 = the synthesis input is first
+ * copied into those order-major tiles and read from there (else gathered
+ * from the spectrum directly)), or read the one in use.  Results do not change.
  * SHT_ERR_INVALID_ARG while graphs of the plan exist (they hold the old work
  * list). */
 sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb, int staged);

@@ -24,7 +24,7 @@ EXPORTS = ["sht_plan", "sht_plan_destroy", "sht_plan_segment", "sht_plan_sizes",
 OPS = {"sht": 0, "isht": 1, "sht_T": 2, "isht_T": 3}
 
 TIMING_KINDS = ["dft_forward", "dft_inverse", "legendre_analysis", "legendre_synthesis", "zero_fill",
-                "channel_mix", "scores", "noise", "transpose"]
+                "channel_mix", "scores", "noise", "transpose", "stage"]
 
 
 class ShtDesc(ctypes.Structure):

@@ -458,7 +458,7 @@ hipStream_t pick_stream(const sht_plan_s* p, void* s) {
 
 enum Kind {
   K_DFT_FWD = 0, K_DFT_INV = 1, K_LEG_ANA = 2, K_LEG_SYN = 3, K_ZERO = 4, K_MIX = 5, K_SCORE = 6, K_NOISE = 7,
-  K_TRANSPOSE = 8
+  K_TRANSPOSE = 8, K_STAGE = 9
 };
 
 hipEvent_t take_event(sht_plan_s* p) {
@@ -473,14 +473,31 @@ hipEvent_t take_event(sht_plan_s* p) {
 }
 
 // Launch `fn` (returning hipError_t) bracketed by timing events when enabled.
+// SHT_DEBUG=1 in the environment: synchronise the stream after every
+// kernel launch of the library (outside stream capture) so that a kernel
+// fault is reported by the call that launched the kernel.
+bool debug_sync() {
+  const char* e = std::getenv("SHT_DEBUG");
+  return e && std::atoi(e) != 0;
+}
+
+hipError_t debug_check(hipStream_t st, hipError_t e) {
+  if (e != hipSuccess || !debug_sync()) return e;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return e;
+  e = hipStreamSynchronize(st);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
 template <typename Fn>
 hipError_t timed(sht_plan_s* p, int kind, hipStream_t st, Fn&& fn) {
-  if (!p->timing) return fn();
+  if (!p->timing) return debug_check(st, fn());
   hipEvent_t a = take_event(p), b = take_event(p);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, st);
   if (e == hipSuccess) e = fn();
   if (e == hipSuccess) e = hipEventRecord(b, st);
+  e = debug_check(st, e);
   if (e == hipSuccess) {
     p->pending.push_back(TimedLaunch{kind, a, b});
   } else {
@@ -521,14 +538,17 @@ sht_status run(sht_plan_s* plan, Op op, const void* in, void* out, void* stream)
       e = timed(plan, K_DFT_FWD, st,
                 [&] { return launch_dft_forward_batched(B, static_cast<const float*>(in), fwd, st); });
       if (e == hipSuccess) e = timed(plan, K_LEG_ANA, st, [&] { return legendre(true, nullptr, out, fwd ? 1.f : 2.f); });
-      if (e == hipSuccess && B.staged)
+      if (e == hipSuccess && (B.staged & 1))
         e = timed(plan, K_TRANSPOSE, st, [&] { return launch_spectrum_transpose(B, static_cast<float2*>(out), st); });
       break;
     }
     case Op::ISHT:
     case Op::SHT_T: {
       const bool inv = (op == Op::ISHT);
-      e = timed(plan, K_LEG_SYN, st, [&] { return legendre(false, in, nullptr, 1.f); });
+      if (B.staged & 2)
+        e = timed(plan, K_STAGE, st,
+                  [&] { return launch_spectrum_stage(B, static_cast<const float2*>(in), st); });
+      if (e == hipSuccess) e = timed(plan, K_LEG_SYN, st, [&] { return legendre(false, in, nullptr, 1.f); });
       if (e == hipSuccess)
         e = timed(plan, K_DFT_INV, st, [&] {
           return launch_dft_inverse_batched(B, static_cast<float*>(out), !inv, inv ? 2.f : 1.f, st);
@@ -604,6 +624,17 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
     if (p->bwork) (void)hipFree(p->bwork);
     delete p;
     return rc;
+  }
+  // SHT_AUTOTUNE=1: run the schedule autotuner on every new plan, with the
+  // cache file named by SHT_TUNE_CACHE (if set)
+  const char* at = std::getenv("SHT_AUTOTUNE");
+  if (at && std::atoi(at) != 0) {
+    rc = sht_plan_tune(p, std::getenv("SHT_TUNE_CACHE"), nullptr, nullptr);
+    if (rc != SHT_OK) {
+      const std::string why = g_last_error;
+      (void)sht_plan_destroy(p);
+      return fail(rc, "autotuning the new plan: %s", why.c_str());
+    }
   }
   *out = p;
   return SHT_OK;
@@ -816,7 +847,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
     int chunk, policy, ncb, staged;
   };
   std::vector<Cand> cands;
-  for (int staged : {1, 0}) {
+  for (int staged : {plan->tune_staged, plan->tune_staged ^ 1, plan->tune_staged ^ 2, plan->tune_staged ^ 3}) {
     for (Cand c : {Cand{8, 0, 2, staged}, Cand{4, 0, 2, staged}, Cand{16, 0, 2, staged}, Cand{32, 0, 2, staged},
                    Cand{8, 1, 2, staged}, Cand{16, 1, 2, staged}})
       cands.push_back(c);
@@ -844,7 +875,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
              static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
     key += buf;
   }
-  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v3";
+  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v4";
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
@@ -989,7 +1020,7 @@ sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb
   if (chunk < 1 || chunk > 64) return fail(SHT_ERR_INVALID_ARG, "chunk must be in [1, 64]");
   if (policy != 0 && policy != 1) return fail(SHT_ERR_INVALID_ARG, "policy must be 0 or 1");
   if (!legendre_ncb_supported(ncb)) return fail(SHT_ERR_INVALID_ARG, "ncb must be 2, 3 or 4");
-  if (staged != 0 && staged != 1) return fail(SHT_ERR_INVALID_ARG, "staged must be 0 or 1");
+  if (staged < 0 || staged > 3) return fail(SHT_ERR_INVALID_ARG, "staged must be in [0, 3]");
   plan->tune_chunk = chunk;
   plan->tune_policy = policy;
   plan->tune_ncb = ncb;

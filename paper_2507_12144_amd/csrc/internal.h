@@ -82,7 +82,8 @@ struct BatchArgs {
   int dft_total;           // DFT items of all segments
   size_t dft_lds;          // dynamic LDS of the batched DFT kernels
   int ncb;                 // field groups per column chunk (workgroup) of the Legendre kernels
-  int staged;              // analysis writes tiles to ystage, then the spectrum transpose runs
+  int staged;              // bit 0: the analysis writes tiles to ystage, then the spectrum transpose
+                           // runs; bit 1: the spectrum is staged first and the synthesis reads ystage
   int tr_total;            // spectrum-transpose tiles of all segments
 };
 // Field groups per column chunk of the bf16 Legendre kernels (the float32
@@ -131,6 +132,9 @@ hipError_t launch_legendre_synthesis_bf16_batched(const BatchArgs& b, int planes
 // whole spectrum, zeros for l < m included).
 int spectrum_transpose_tiles(const SegGeom& g);
 hipError_t launch_spectrum_transpose(const BatchArgs& b, float2* y, hipStream_t st);
+// The reverse: the live entries of y into the staging tiles, which the
+// synthesis reads when BatchArgs::staged has bit 1 set.
+hipError_t launch_spectrum_stage(const BatchArgs& b, const float2* y, hipStream_t st);
 
 // ---- scores.hip ----------------------------------------------------------
 // Angular PSD (App. F.7, eq. psd): out[f][l] = sum_{m <= min(l, mmax-1)} c_m |y[f][l][m]|^2.

@@ -186,7 +186,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[kb + 4 * t + 3], acc, 0, 0, 0);
           }
           if constexpr (part == PARTS - 1) {
-            if (staged) {
+            if (staged & 1) {
               // the 16 x 16 tile, contiguous, into the order-major staging
               // buffer (rows past the parity's last degree hold zeros)
               float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
   // degree l = m for its fields, y[f][m][m+1 .. mmax-1], one contiguous run
   // per field, instead of the scattered column y[f][0 .. m-1][m].  (Staged:
   // the transpose writes them.)
-  if (!staged && m < g.lmax) {
+  if (!(staged & 1) && m < g.lmax) {
     const int fbeg = 8 * NCB * c;
     const int fend = min(g.F, fbeg + 8 * NCB);
     const int run = g.mmax - 1 - m;
@@ -235,7 +235,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
 // + lk.  Piece e of a row block is substep e / (KR/4), piece e % (KR/4).
 template <int NCB, int KS>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               float* __restrict__ W, v4f* b0, v4f* b1, v4f* b2, float* spec) {
+                                               float* __restrict__ W, int staged, v4f* b0, v4f* b1, v4f* b2,
+                                               float* spec) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
@@ -270,13 +271,27 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   const bool fok = active && f < g.F;
   const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
   float* wspec = spec + wave * 256;
+  // Staged input: the same values from the order-major staging tiles
+  // (row i of parity p, column li of group cb: 64 contiguous bytes per
+  // four lanes' rows), rows past the parity's last degree from row 0 of
+  // parity 0 (degree m).
+  const int nbs = (((g.lmax - m + 1) >> 1) + 15) >> 4;
+  const float* ystg = sd.ystage + sd.ystage_off[m];
+  const int cbs = active ? cb : 0;
   auto spec_copy = [&](int ib) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = 16 * ib + 4 * s + lk;
-      const int l = i < np ? m + p + 2 * i : m;
-      __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
-                                       wspec + 64 * s, 4, 0, 0);
+      if (staged & 2) {
+        const bool in = i < np;
+        const float* src = ystg + ((static_cast<size_t>(in ? p : 0) * g.groups + cbs) * nbs) * 256 +
+                           static_cast<size_t>(in ? i : 0) * 16 + li;
+        __builtin_amdgcn_global_load_lds(src, wspec + 64 * s, 4, 0, 0);
+      } else {
+        const int l = i < np ? m + p + 2 * i : m;
+        __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
+                                         wspec + 64 * s, 4, 0, 0);
+      }
     }
   };
   floatx4 acc[KR];
@@ -378,7 +393,8 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
 
 template <int NCB>
 __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) void synthesis_batched(
-    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y) {
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y,
+    int staged) {
   __shared__ v4f b0[kMaxStagePieces * 64], b1[kMaxStagePieces * 64], b2[kMaxStagePieces * 64];
   __shared__ float spec[2 * NCB * 256];  // spectrum slot: 1 KiB per wave
   const int2 wk = take_work(work, per);
@@ -387,11 +403,11 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const int m = wk.x, c = wk.y & 0xffff;
   const float2* ys = y + sd.spec_off;
   switch (sd.g.kpad) {
-    case 64: synthesis_body<NCB, 16>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
-    case 128: synthesis_body<NCB, 32>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
-    case 192: synthesis_body<NCB, 48>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
-    case 256: synthesis_body<NCB, 64>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
-    default: synthesis_body<NCB, 96>(sd, m, c, ys, sd.work, b0, b1, b2, spec); break;
+    case 64: synthesis_body<NCB, 16>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
+    case 128: synthesis_body<NCB, 32>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
+    case 192: synthesis_body<NCB, 48>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
+    case 256: synthesis_body<NCB, 64>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
+    default: synthesis_body<NCB, 96>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
   }
 }
 
@@ -404,7 +420,7 @@ hipError_t launch_ncb(bool analysis, const BatchArgs& b, const float2* in, float
   if (analysis)
     hipLaunchKernelGGL(analysis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, out, c_rest, b.staged);
   else
-    hipLaunchKernelGGL(synthesis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, in);
+    hipLaunchKernelGGL(synthesis_batched<NCB>, grid, block, 0, st, b.segs, b.work, b.work_per, in, b.staged);
   return hipGetLastError();
 }
 

@@ -245,7 +245,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
             products<NP, ND>(av, xs[part * SS + s], main, corr);
           }
           if constexpr (part == PARTS - 1) {
-            if (staged) {
+            if (staged & 1) {
               // the 16 x 16 tile, contiguous, into the order-major staging buffer
               float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
 #pragma unroll
@@ -278,7 +278,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   // zeros of the spectrum: degree l = m, orders m+1 .. mmax-1 of this
   // chunk's fields (contiguous runs; the orders together cover every l < m';
   // staged: the transpose writes them)
-  if (!staged && m < g.lmax) {
+  if (!(staged & 1) && m < g.lmax) {
     const int fbeg = 16 * c;
     const int fend = min(g.F, fbeg + 16);
     const int run = g.mmax - 1 - m;
@@ -297,7 +297,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
 // wait is one of the counted waits below.
 template <int KS, int NP, int NBUF>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               v4f* ring, float* spec) {
+                                               int staged, v4f* ring, float* spec) {
   constexpr int KPAD = 4 * KS;
   constexpr int KR = KPAD / 16;  // steps (16-ring output blocks) per 32-row block
   using G = Geo<KR, NP, KS / 8, NBUF, 2>;
@@ -326,13 +326,25 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   const bool fok = active && f < g.F;
   const size_t fbase = (static_cast<size_t>(fok ? f : 0) * g.lmax) * g.mmax;
   float* wspec = spec + wave * 64 * NB;
+  // Staged input: the same values from the order-major staging tiles (rows
+  // past the parity's last degree from row 0 of parity 0, degree m).
+  const int nbs = (((g.lmax - m + 1) >> 1) + 15) >> 4;
+  const float* ystg = sd.ystage + sd.ystage_off[m];
+  const int cbs = active ? cb : 0;
   auto spec_copy = [&](int ib) {
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
       const int i = 32 * ib + 8 * lk + e;
-      const int l = i < np ? m + p + 2 * i : m;
-      __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
-                                       wspec + 64 * e, 4, 0, 0);
+      if (staged & 2) {
+        const bool in = i < np;
+        const float* src = ystg + ((static_cast<size_t>(in ? p : 0) * g.groups + cbs) * nbs) * 256 +
+                           static_cast<size_t>(in ? i : 0) * 16 + li;
+        __builtin_amdgcn_global_load_lds(src, wspec + 64 * e, 4, 0, 0);
+      } else {
+        const int l = i < np ? m + p + 2 * i : m;
+        __builtin_amdgcn_global_load_lds(yf + (fbase + static_cast<size_t>(l) * g.mmax + m) * 2 + (li & 1),
+                                         wspec + 64 * e, 4, 0, 0);
+      }
     }
   };
   floatx4 acc[KR];
@@ -422,7 +434,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
 
 template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void synthesis_batched(
-    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y) {
+    const SegDev* __restrict__ segs, const int2* __restrict__ work, int per, const float2* __restrict__ y,
+    int staged) {
   // one LDS variable for the ring and the spectrum slot: the compiler then
   // leaves the copies to the counted waits instead of waiting for the
   // newest copy into a variable before every read of it
@@ -436,11 +449,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const float2* ys = y + sd.spec_off;
   constexpr int R = kSynBuffers;
   switch (sd.g.kpad) {
-    case 64: synthesis_body<16, NP, R>(sd, m, c, ys, ring, spec); break;
-    case 128: synthesis_body<32, NP, R>(sd, m, c, ys, ring, spec); break;
-    case 192: synthesis_body<48, NP, R>(sd, m, c, ys, ring, spec); break;
-    case 256: synthesis_body<64, NP, R>(sd, m, c, ys, ring, spec); break;
-    default: synthesis_body<96, NP, R>(sd, m, c, ys, ring, spec); break;
+    case 64: synthesis_body<16, NP, R>(sd, m, c, ys, staged, ring, spec); break;
+    case 128: synthesis_body<32, NP, R>(sd, m, c, ys, staged, ring, spec); break;
+    case 192: synthesis_body<48, NP, R>(sd, m, c, ys, staged, ring, spec); break;
+    case 256: synthesis_body<64, NP, R>(sd, m, c, ys, staged, ring, spec); break;
+    default: synthesis_body<96, NP, R>(sd, m, c, ys, staged, ring, spec); break;
   }
 }
 
@@ -453,7 +466,7 @@ hipError_t launch_batched(bool analysis, const BatchArgs& b, const void* in, voi
                        static_cast<float2*>(out), c_rest, b.staged);
   else
     hipLaunchKernelGGL(synthesis_batched<NP>, grid, dim3(256), 0, st, b.segs, b.work, b.work_per,
-                       static_cast<const float2*>(in));
+                       static_cast<const float2*>(in), b.staged);
   return hipGetLastError();
 }
 

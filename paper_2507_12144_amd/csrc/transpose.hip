@@ -95,7 +95,69 @@ __global__ __launch_bounds__(NTR) void spectrum_transpose_kernel(const SegDev* _
   }
 }
 
+// The reverse move for the staged synthesis input: y[f][l][m] (live entries
+// m <= l) into the order-major tiles Y' that the synthesis then reads as
+// contiguous rows instead of gathering 4-byte values from the m-fastest
+// spectrum.  Same tiling; tiles with no live entry do nothing; rows of
+// degrees past lmax are not written (the synthesis never reads them).
+__global__ __launch_bounds__(NTR) void spectrum_stage_kernel(const SegDev* __restrict__ segs, int nseg, int total,
+                                                             const float2* __restrict__ y) {
+  __shared__ float2 T[8][TL][TM + 1];  // [field][degree][order]
+  const int t = blockIdx.x;
+  if (t >= total) return;
+  const SegDev& sd = segs[segment_of_tile(segs, nseg, t)];
+  const SegGeom& g = sd.g;
+  const int lt = (g.lmax + TL - 1) / TL, mt = (g.mmax + TM - 1) / TM;
+  int loc = t - sd.tr_begin;
+  const int gi = loc / (lt * mt);
+  loc -= gi * lt * mt;
+  const int l0 = (loc / mt) * TL, m0 = (loc % mt) * TM;
+  if (m0 > l0 + TL - 1) return;  // every order of the tile is above every degree
+  const float2* ys = y + sd.spec_off;
+  // load y[f][l][m0 .. m0+31] of the group's fields (zeros for fields past F,
+  // orders past mmax and degrees past lmax)
+  for (int idx = threadIdx.x; idx < 8 * TL * (TM / 2); idx += NTR) {
+    const int q = idx % (TM / 2);
+    const int li = (idx / (TM / 2)) % TL;
+    const int fl = idx / (TL * TM / 2);
+    const int f = 8 * gi + fl, l = l0 + li, m = m0 + 2 * q;
+    float2 a = make_float2(0.f, 0.f), b = a;
+    if (f < g.F && l < g.lmax && m < g.mmax) {
+      const float2* src = ys + (static_cast<size_t>(f) * g.lmax + l) * g.mmax + m;
+      a = src[0];
+      if (m + 1 < g.mmax) b = src[1];
+    }
+    T[fl][li][2 * q] = a;
+    T[fl][li][2 * q + 1] = b;
+  }
+  __syncthreads();
+  // write the staging rows: (order, parity) pairs, 8 rows of 16 floats each
+  for (int idx = threadIdx.x; idx < TM * 2 * 8 * 4; idx += NTR) {
+    const int q = idx & 3;
+    const int row = (idx >> 2) & 7;
+    const int par = (idx >> 5) & 1;
+    const int mi = idx >> 6;
+    const int m = m0 + mi;
+    const int first = l0 + ((m + par - l0) & 1);
+    const int l = first + 2 * row;
+    if (m >= g.mmax || l >= g.lmax || l < m) continue;
+    const int li = l - l0;
+    const int i = (l - m) >> 1;
+    const int nbm = (((g.lmax - m + 1) >> 1) + 15) >> 4;
+    float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(par) * g.groups + gi) * nbm) * 256 +
+                 static_cast<size_t>(i) * 16 + 4 * q;
+    const float2 a = T[2 * q][li][mi], b = T[2 * q + 1][li][mi];
+    *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, b.x, b.y);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_spectrum_stage(const BatchArgs& b, const float2* y, hipStream_t st) {
+  hipLaunchKernelGGL(spectrum_stage_kernel, dim3(static_cast<unsigned>(b.tr_total)), dim3(NTR), 0, st, b.segs,
+                     b.nseg, b.tr_total, y);
+  return hipGetLastError();
+}
 
 int spectrum_transpose_tiles(const SegGeom& g) {
   return g.groups * ((g.lmax + TL - 1) / TL) * ((g.mmax + TM - 1) / TM);

@@ -718,7 +718,7 @@ def test_field_groups_per_workgroup_are_bitwise_equal(pkg, shape):
     u = _to_dev(synth.grid_normal(31, (B, C, nlat, nlon)), torch.float32)
     a = _to_dev(synth.coefficients(32, B, C, L, M), torch.complex64)
     ref = None
-    for staged in (0, 1):
+    for staged in (0, 1, 2, 3):
         for ncb in (2, 3, 4):
             plan.set_schedule(8, 0, ncb, staged)
             assert plan.schedule() == (8, 0, ncb, staged)
@@ -733,8 +733,9 @@ def test_field_groups_per_workgroup_are_bitwise_equal(pkg, shape):
 
 @pytest.mark.parametrize("prec", ["bf16", "bf16x2", "bf16x3"])
 def test_staged_analysis_bitwise_equal_bf16_forms(pkg, prec):
-    """Staged and direct analysis output of the bf16 forms, bitwise, on a
-    multi-segment plan (every ring padding, odd mmax, mmax < lmax)."""
+    """Staged and direct analysis output and synthesis input of the bf16
+    forms, bitwise, on a multi-segment plan (every ring padding, odd mmax,
+    mmax < lmax)."""
     shapes = [(33, 64, 17, 17, 0, 1, 3), (65, 128, 64, 41, 0, 2, 3), (181, 360, 180, 180, 0, 1, 5),
               (721, 1440, 720, 720, 0, 1, 2)]
     _say("staged bf16", prec)
@@ -742,9 +743,44 @@ def test_staged_analysis_bitwise_equal_bf16_forms(pkg, prec):
     u_h, _, _ = _batched_io(pkg, plan, shapes, seed=33)
     u = _to_dev(u_h, torch.float32)
     mask = _segment_mask(plan, shapes, True)
+    a_h = np.zeros(plan.spec_elems, np.complex64)
+    for i, (nlat, nlon, lmax, mmax, grid, B, C) in enumerate(shapes):
+        _, so = plan.segment(i)
+        ai = synth.coefficients(34 + i, B, C, lmax, mmax).astype(np.complex64)
+        a_h[so:so + ai.size] = ai.ravel()
+    a = _to_dev(a_h, torch.complex64)
+    gmask = _segment_mask(plan, shapes, False)
     outs = []
-    for staged in (0, 1):
+    for staged in (0, 1, 2, 3):
         plan.set_schedule(8, 0, 2, staged)
-        outs.append((plan.sht(u).cpu().numpy()[mask], plan.isht_T(u).cpu().numpy()[mask]))
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+        outs.append((plan.sht(u).cpu().numpy()[mask], plan.isht_T(u).cpu().numpy()[mask],
+                     plan.isht(a).cpu().numpy()[gmask], plan.sht_T(a).cpu().numpy()[gmask]))
+    for o in outs[1:]:
+        for x, r in zip(o, outs[0]):
+            assert np.array_equal(x, r)
     plan.close()
+
+
+def test_environment_switches(pkg, tmp_path):
+    """SHT_AUTOTUNE=1 tunes every new plan (its choice lands in the
+    SHT_TUNE_CACHE file); SHT_DEBUG=1 synchronises after every kernel and
+    leaves the results unchanged."""
+    _say("environment switches")
+    shape = (33, 64, 17, 17, 0, 1, 3)
+    u = _to_dev(synth.grid_normal(41, (1, 3, 33, 64)), torch.float32)
+    plan = _plan(pkg, *shape)
+    ref = plan.sht(u).cpu().numpy()
+    plan.close()
+    cache = tmp_path / "tune.txt"
+    os.environ["SHT_AUTOTUNE"] = "1"
+    os.environ["SHT_TUNE_CACHE"] = str(cache)
+    os.environ["SHT_DEBUG"] = "1"
+    try:
+        plan = _plan(pkg, *shape)
+        got = plan.sht(u).cpu().numpy()
+        plan.close()
+    finally:
+        for k in ("SHT_AUTOTUNE", "SHT_TUNE_CACHE", "SHT_DEBUG"):
+            os.environ.pop(k, None)
+    assert cache.exists() and len(cache.read_text().splitlines()) == 1
+    assert np.array_equal(got, ref)
