@@ -322,8 +322,8 @@ sht_status sht_graph_launch(sht_graph_t graph, void* hip_stream);
 sht_status sht_graph_destroy(sht_graph_t graph);
 
 /* Autotuner.  The work decomposition of a plan has free parameters that do
- * not change any result bit: whether the analysis output is staged in
- * order-major tiles and transposed (see sht_plan_set_schedule), the field
+ * not change any result bit: whether the analysis output and the synthesis
+ * input pass through order-major tiles (see sht_plan_set_schedule), the field
  * groups (of 8 fields) per workgroup of the float32 Legendre kernels (2, 3
  * or 4; the bf16 forms always take 2),
  * the orders per scheduling chunk of the Legendre work list (4, 8, 16, 32)
@@ -350,6 +350,9 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
  * stores into the spectrum directly), bit 1 = the synthesis input is first
  * copied into those order-major tiles and read from there (else gathered
  * from the spectrum directly)), or read the one in use.  Results do not change.
+ * A new plan starts at chunk 8, policy 0, ncb 2 and staged 3 when a segment
+ * has 256 or more fields, else staged 1 for the split bf16 forms and 0
+ * otherwise.
  * SHT_ERR_INVALID_ARG while graphs of the plan exist (they hold the old work
  * list). */
 sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb, int staged);

@@ -586,12 +586,16 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
   if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
   p->prec = prec;
   p->storage = storage_of(prec);
-  // Staged analysis output by default only for the split bf16 forms: there
-  // the scattered spectrum stores cost more than the transpose that replaces
-  // them (measured at 721 x 1440, 72 fields: 387 -> 267 + 107 us); for
-  // float32 and plain bf16 the direct stores are a little cheaper.  The
-  // tuner measures both.
-  p->tune_staged = (p->storage == Storage::BF16X2 || p->storage == Storage::BF16X3) ? 1 : 0;
+  // Default staging (the tuner measures all four modes).  With many fields
+  // per segment both directions are staged: the scattered 8-byte spectrum
+  // stores and 4-byte gathers then cost far more than the transposes that
+  // replace them (360 x 720 Gauss grid, 4 x 256 fields: step 13.16 ->
+  // 11.77 ms).  At 72 fields on 721 x 1440 only the split bf16 forms stage
+  // their analysis output (387 -> 267 + 107 us); for float32 and plain
+  // bf16 the direct stores and gathers are a little cheaper.
+  int max_fields = 0;
+  for (int i = 0; i < ndesc; ++i) max_fields = std::max(max_fields, descs[i].batch * descs[i].channels);
+  p->tune_staged = max_fields >= 256 ? 3 : (p->storage == Storage::BF16X2 || p->storage == Storage::BF16X3) ? 1 : 0;
   p->stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
@@ -875,7 +879,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
              static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
     key += buf;
   }
-  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v4";
+  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v5";
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;

@@ -233,10 +233,9 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
 // Synthesis.  Output ring k of a wave's block = li * KR + 4t + q for MFMA row
 // li, piece t of a substep and component q; contraction row i = 16 ib + 4 s
 // + lk.  Piece e of a row block is substep e / (KR/4), piece e % (KR/4).
-template <int NCB, int KS>
+template <int NCB, int KS, bool STG>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               float* __restrict__ W, int staged, v4f* b0, v4f* b1, v4f* b2,
-                                               float* spec) {
+                                               float* __restrict__ W, v4f* b0, v4f* b1, v4f* b2, float* spec) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, PARTS = S::PARTS, T4 = S::T4;
   constexpr int KPAD = 4 * KS;
@@ -282,7 +281,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = 16 * ib + 4 * s + lk;
-      if (staged & 2) {
+      if constexpr (STG) {
         const bool in = i < np;
         const float* src = ystg + ((static_cast<size_t>(in ? p : 0) * g.groups + cbs) * nbs) * 256 +
                            static_cast<size_t>(in ? i : 0) * 16 + li;
@@ -402,12 +401,21 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const SegDev& sd = segs[wk.y >> 16];
   const int m = wk.x, c = wk.y & 0xffff;
   const float2* ys = y + sd.spec_off;
+  // the input source is a compile-time choice: a run-time branch in the
+  // copy loop costs the direct form about a tenth of its time
+  auto body = [&](auto ks_c) {
+    constexpr int KS = decltype(ks_c)::value;
+    if (staged & 2)
+      synthesis_body<NCB, KS, true>(sd, m, c, ys, sd.work, b0, b1, b2, spec);
+    else
+      synthesis_body<NCB, KS, false>(sd, m, c, ys, sd.work, b0, b1, b2, spec);
+  };
   switch (sd.g.kpad) {
-    case 64: synthesis_body<NCB, 16>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
-    case 128: synthesis_body<NCB, 32>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
-    case 192: synthesis_body<NCB, 48>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
-    case 256: synthesis_body<NCB, 64>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
-    default: synthesis_body<NCB, 96>(sd, m, c, ys, sd.work, staged, b0, b1, b2, spec); break;
+    case 64: body(std::integral_constant<int, 16>{}); break;
+    case 128: body(std::integral_constant<int, 32>{}); break;
+    case 192: body(std::integral_constant<int, 48>{}); break;
+    case 256: body(std::integral_constant<int, 64>{}); break;
+    default: body(std::integral_constant<int, 96>{}); break;
   }
 }
 
