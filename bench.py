@@ -88,29 +88,37 @@ def legendre_bytes(nlat, lmax, mmax, fields, precision):
     return pairs * nk * TABLE_BYTES[precision] + fields * lmax * mmax * 8
 
 
-def profiled_traffic(kind, precision):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
-    or None when there is no summary for this precision or the kernel source
-    has changed since the counters were taken."""
+def profiled_traffic(kind, precision, extra=None):
+    """HBM bytes per launch of the dominant kernel (plus, with extra, of the
+    transpose or staging kernel charged to it) from the committed rocprofv3
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known
+    size), or None when there is no summary for this precision or a kernel
+    source has changed since the counters were taken."""
     import glob
     import hashlib
-    src_file = "legendre.h" if precision == "fp32" else "legendre_bf16.h"
-    src_key = "legendre" if precision == "fp32" else "legendre_bf16"
-    with open(os.path.join(ROOT, "paper_2507_12144_amd", "csrc", src_file), "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    prefix = "analysis" if kind == "legendre_analysis" else "synthesis"
+
+    def sha(name):
+        with open(os.path.join(ROOT, "paper_2507_12144_amd", "csrc", name), "rb") as fh:
+            return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+    want = {"legendre" if precision == "fp32" else "legendre_bf16":
+            sha("legendre.h" if precision == "fp32" else "legendre_bf16.h")}
+    if extra:
+        want["transpose"] = sha("transpose.hip")
+    prefixes = ["analysis" if kind == "legendre_analysis" else "synthesis"] + ([extra] if extra else [])
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
             for line in fh:
                 if not line.startswith("traffic_json: "):
                     continue
                 rec = json.loads(line[len("traffic_json: "):])
-                if rec.get("precision") != precision or rec["source_sha256_16"].get(src_key) != sha:
+                if rec.get("precision") != precision or any(rec["source_sha256_16"].get(k) != v
+                                                            for k, v in want.items()):
                     continue
-                for name, nbytes in rec["hbm_bytes_per_launch"].items():
-                    if name.startswith(prefix):
-                        return {"hbm_bytes_per_launch": nbytes, "source": os.path.relpath(path, ROOT)}
+                got = [v for pre in prefixes for name, v in rec["hbm_bytes_per_launch"].items()
+                       if name.startswith(pre)]
+                if len(got) == len(prefixes):
+                    return {"hbm_bytes_per_launch": sum(got), "source": os.path.relpath(path, ROOT)}
     return None
 
 
@@ -542,7 +550,9 @@ def main():
         peaks = P.measure_peaks()
         roofline["peak_measured"] = peaks["fp32_mfma_TFs"] if args.precision == "fp32" else peaks["hbm_measured_GBs"]
         roofline["frac_measured"] = round(achieved / roofline["peak_measured"], 4)
-    prof = profiled_traffic(kind, args.precision)
+    prof = profiled_traffic(kind, args.precision,
+                            "spectrum_transpose" if extra == " + spectrum transpose" else
+                            "spectrum_stage" if extra == " + input staging" else None)
     if prof is not None:
         roofline["traffic"] = prof["hbm_bytes_per_launch"]
         roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
