@@ -54,16 +54,20 @@ __device__ __forceinline__ U64x4 philox4x64_10(unsigned long long c0, unsigned l
   return x;
 }
 
-__global__ __launch_bounds__(256) void noise_step_kernel(long long total, int channels, int lmax, int mmax,
+// Grid: x = spectral row (f, l) of the batch, y = 256-order slice of the
+// row; all index arithmetic in 32 bits (64-bit divisions are emulated and
+// cost more than the generator).
+__global__ __launch_bounds__(256) void noise_step_kernel(int channels, int lmax, int mmax,
                                                          const double* __restrict__ sigma_l,
                                                          const double* __restrict__ phi, unsigned long long seed,
                                                          unsigned long long step, float2* __restrict__ y) {
-  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int m = static_cast<int>(i % mmax);
-  const long long fl = i / mmax;
-  const int l = static_cast<int>(fl % lmax);
-  const int c = static_cast<int>((fl / lmax) % channels);
+  const int row = static_cast<int>(blockIdx.x);
+  const int m = static_cast<int>(blockIdx.y) * 256 + static_cast<int>(threadIdx.x);
+  if (m >= mmax) return;
+  const int f = row / lmax;
+  const int l = row - f * lmax;
+  const int c = f % channels;
+  const long long i = static_cast<long long>(row) * mmax + m;
   if (l < 1 || m > l) {
     y[i] = make_float2(0.f, 0.f);
     return;
@@ -104,10 +108,11 @@ __global__ __launch_bounds__(256) void noise_step_kernel(long long total, int ch
 
 hipError_t launch_noise_step(int batch, int channels, int lmax, int mmax, const double* sigma_l, const double* phi,
                              unsigned long long seed, unsigned long long step, float2* y, hipStream_t st) {
-  const long long total = static_cast<long long>(batch) * channels * lmax * mmax;
-  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-  hipLaunchKernelGGL(noise_step_kernel, dim3(blocks), dim3(256), 0, st, total, channels, lmax, mmax, sigma_l, phi,
-                     seed, step, y);
+  const long long rows = static_cast<long long>(batch) * channels * lmax;
+  if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (rows == 0 || mmax <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(rows), static_cast<unsigned>((mmax + 255) / 256));
+  hipLaunchKernelGGL(noise_step_kernel, grid, dim3(256), 0, st, channels, lmax, mmax, sigma_l, phi, seed, step, y);
   return hipGetLastError();
 }
 
