@@ -160,14 +160,12 @@ __global__ __launch_bounds__(256) void channel_mix_kernel(int B, int C, int lmax
 }
 
 // out[b, c, l, m] = 0 for m > l (the part the mix kernel never writes).
-__global__ void mix_zero_kernel(int B, int C, int lmax, int mmax, float2* __restrict__ out) {
-  const size_t total = static_cast<size_t>(B) * C * lmax * mmax;
-  for (size_t idx = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; idx < total;
-       idx += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int m = static_cast<int>(idx % mmax);
-    const int l = static_cast<int>((idx / mmax) % lmax);
-    if (m > l) out[idx] = make_float2(0.f, 0.f);
-  }
+// Grid: x = spectral row (b, c, l), y = 256-order slice; 32-bit indices.
+__global__ __launch_bounds__(256) void mix_zero_kernel(int lmax, int mmax, float2* __restrict__ out) {
+  const int row = static_cast<int>(blockIdx.x);
+  const int m = static_cast<int>(blockIdx.y) * 256 + static_cast<int>(threadIdx.x);
+  const int l = row % lmax;
+  if (m > l && m < mmax) out[static_cast<long long>(row) * mmax + m] = make_float2(0.f, 0.f);
 }
 
 // Weight gradient of the mix: dW[l, c', c] = sum_{b, m <= l} g[b, c', l, m]
@@ -237,16 +235,18 @@ __global__ __launch_bounds__(256) void mix_weight_grad_kernel(int B, int C, int 
 // s2_spectral_conv: out[b,c,l,m] = k[c,l] in[b,c,l,m] (adjoint: conj(k)),
 // 0 for m > l.  Elementwise and HBM-bound: one thread per coefficient,
 // consecutive threads on consecutive m.
-__global__ __launch_bounds__(256) void isotropic_filter_kernel(long long total, int C, int lmax, int mmax,
+// Grid: x = spectral row (b, c, l), y = 256-order slice; 32-bit indices.
+__global__ __launch_bounds__(256) void isotropic_filter_kernel(int C, int lmax, int mmax,
                                                                const float2* __restrict__ k,
                                                                const float2* __restrict__ in,
                                                                float2* __restrict__ out, int adjoint) {
-  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int m = static_cast<int>(i % mmax);
-  const long long r = i / mmax;
-  const int l = static_cast<int>(r % lmax);
-  const int c = static_cast<int>((r / lmax) % C);
+  const int row = static_cast<int>(blockIdx.x);
+  const int m = static_cast<int>(blockIdx.y) * 256 + static_cast<int>(threadIdx.x);
+  if (m >= mmax) return;
+  const int f = row / lmax;
+  const int l = row - f * lmax;
+  const int c = f % C;
+  const long long i = static_cast<long long>(row) * mmax + m;
   if (m > l) {
     out[i] = make_float2(0.f, 0.f);
     return;
@@ -308,11 +308,11 @@ hipError_t launch_channel_mix(int batch, int channels, int lmax, int mmax, const
                      out, adjoint);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t total = static_cast<size_t>(batch) * channels * lmax * mmax;
-  size_t blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(mix_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, batch,
-                     channels, lmax, mmax, out);
+  const long long rows = static_cast<long long>(batch) * channels * lmax;
+  if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (rows == 0 || mmax <= 0) return hipSuccess;
+  const dim3 zgrid(static_cast<unsigned>(rows), static_cast<unsigned>((mmax + 255) / 256));
+  hipLaunchKernelGGL(mix_zero_kernel, zgrid, dim3(256), 0, stream, lmax, mmax, out);
   return hipGetLastError();
 }
 
@@ -322,9 +322,12 @@ namespace sht {
 
 hipError_t launch_isotropic_filter(int batch, int channels, int lmax, int mmax, const float2* k, const float2* in,
                                    float2* out, int adjoint, hipStream_t stream) {
-  const long long total = static_cast<long long>(batch) * channels * lmax * mmax;
-  hipLaunchKernelGGL(isotropic_filter_kernel, dim3(static_cast<unsigned>((total + 255) / 256)), dim3(256), 0, stream,
-                     total, channels, lmax, mmax, k, in, out, adjoint);
+  const long long rows = static_cast<long long>(batch) * channels * lmax;
+  if (rows > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (rows == 0 || mmax <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(rows), static_cast<unsigned>((mmax + 255) / 256));
+  hipLaunchKernelGGL(isotropic_filter_kernel, grid, dim3(256), 0, stream, channels, lmax, mmax, k, in, out,
+                     adjoint);
   return hipGetLastError();
 }
 
