@@ -350,9 +350,8 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
  * stores into the spectrum directly), bit 1 = the synthesis input is first
  * copied into those order-major tiles and read from there (else gathered
  * from the spectrum directly)), or read the one in use.  Results do not change.
- * A new plan starts at chunk 8, policy 0, ncb 2 and staged 3 when a segment
- * has 256 or more fields, else staged 1 for the split bf16 forms and 0
- * otherwise.
+ * A new plan starts at chunk 8, policy 0, ncb 2 and staged 3, except
+ * float32 plans whose segments all have fewer than 256 fields: staged 1.
  * SHT_ERR_INVALID_ARG while graphs of the plan exist (they hold the old work
  * list). */
 sht_status sht_plan_set_schedule(sht_plan_t plan, int chunk, int policy, int ncb, int staged);

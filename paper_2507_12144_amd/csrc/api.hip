@@ -586,16 +586,18 @@ sht_status sht_plan(sht_plan_t* out, const sht_desc* descs, int ndesc, sht_preci
   if (!p) return fail(SHT_ERR_OUT_OF_MEMORY, "host allocation");
   p->prec = prec;
   p->storage = storage_of(prec);
-  // Default staging (the tuner measures all four modes).  With many fields
-  // per segment both directions are staged: the scattered 8-byte spectrum
-  // stores and 4-byte gathers then cost far more than the transposes that
-  // replace them (360 x 720 Gauss grid, 4 x 256 fields: step 13.16 ->
-  // 11.77 ms).  At 72 fields on 721 x 1440 only the split bf16 forms stage
-  // their analysis output (387 -> 267 + 107 us); for float32 and plain
-  // bf16 the direct stores and gathers are a little cheaper.
+  // Default staging (the tuner measures all four modes).  The analysis
+  // output always goes through the order-major tiles and the transpose:
+  // its scattered 8-byte spectrum stores cost more than the transpose
+  // (721 x 1440, 72 fields, float32: 429 -> 328 + 72 us).  The synthesis
+  // input does for the bf16 forms, whose contraction is cheap enough that
+  // the 4-byte gathers dominate (split bf16: 341 -> 259 + 68 us), and for
+  // every form once a segment has 256 or more fields (Gauss 360 x 720,
+  // 4 x 256 fields, float32: 1419 -> 658 + 273 us); at 72 fields the float32
+  // synthesis gathers directly (381 against 336 + 67 us).
   int max_fields = 0;
   for (int i = 0; i < ndesc; ++i) max_fields = std::max(max_fields, descs[i].batch * descs[i].channels);
-  p->tune_staged = max_fields >= 256 ? 3 : (p->storage == Storage::BF16X2 || p->storage == Storage::BF16X3) ? 1 : 0;
+  p->tune_staged = (p->storage != Storage::F32 || max_fields >= 256) ? 3 : 1;
   p->stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
@@ -879,7 +881,7 @@ sht_status sht_plan_tune(sht_plan_t plan, const char* cache_path, int* chosen, d
              static_cast<int>(S.d.grid), S.d.batch, S.d.channels);
     key += buf;
   }
-  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v5";
+  key += "|" + std::to_string(static_cast<int>(plan->prec)) + "|v6";
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
