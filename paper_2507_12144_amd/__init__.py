@@ -28,8 +28,10 @@ class Plan:
     (complex64).  With several shapes (the batching form) tensors are flat
     concatenations; ``segment(i)`` gives each shape's offsets."""
 
-    def __init__(self, descs, precision="fp32", device=None):
-        lib = _lib.load()
+    def __init__(self, descs, precision="fp32", device=None, library=None):
+        # library: a handle from _lib.open_library (e.g. the race-check build),
+        # default the package's libsht.so
+        lib = self._lib = library if library is not None else _lib.load()
         if isinstance(descs, dict):
             descs = [descs]
         self.descs = [dict(d) for d in descs]
@@ -44,16 +46,20 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _lib.check(lib.sht_plan(ctypes.byref(self._h), arr, len(self.descs), prec,
+            self._status(lib.sht_plan(ctypes.byref(self._h), arr, len(self.descs), prec,
                                     _stream_ptr(self.device)))
         g, s = ctypes.c_size_t(), ctypes.c_size_t()
-        _lib.check(lib.sht_plan_sizes(self._h, ctypes.byref(g), ctypes.byref(s)))
+        self._status(lib.sht_plan_sizes(self._h, ctypes.byref(g), ctypes.byref(s)))
         self.grid_elems, self.spec_elems = g.value, s.value
+
+    def _status(self, status):
+        if status != _lib.SHT_OK:
+            raise _lib.ShtError(status, self._lib.sht_last_error().decode(errors="replace"))
 
     # ------------------------------------------------------------------ info
     def segment(self, i):
         g, s = ctypes.c_size_t(), ctypes.c_size_t()
-        _lib.check(_lib.load().sht_plan_segment(self._h, i, ctypes.byref(g), ctypes.byref(s)))
+        self._status(self._lib.sht_plan_segment(self._h, i, ctypes.byref(g), ctypes.byref(s)))
         return g.value, s.value
 
     def grid(self, i=0):
@@ -61,7 +67,7 @@ class Plan:
         n = self.descs[i]["nlat"]
         x = (ctypes.c_double * n)()
         w = (ctypes.c_double * n)()
-        _lib.check(_lib.load().sht_plan_grid(self._h, i, x, w))
+        self._status(self._lib.sht_plan_grid(self._h, i, x, w))
         return torch.tensor(list(x), dtype=torch.float64), torch.tensor(list(w), dtype=torch.float64)
 
     def grid_shape(self):
@@ -92,28 +98,28 @@ class Plan:
         if dst is None:
             dst = torch.empty(dshape, dtype=ddt, device=self.device)
         self._check(dst, ddt, dshape, "output")
-        _lib.check(fn(self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+        self._status(fn(self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                       _stream_ptr(self.device)))
         return dst
 
     def sht(self, x, out=None):
         """Forward SHT: float32 grid -> complex64 spectrum."""
-        return self._call(_lib.load().sht_forward, x, torch.float32, self.grid_shape(), out,
+        return self._call(self._lib.sht_forward, x, torch.float32, self.grid_shape(), out,
                           torch.complex64, self.spec_shape())
 
     def isht(self, y, out=None):
         """Inverse SHT: complex64 spectrum -> float32 grid."""
-        return self._call(_lib.load().isht_forward, y, torch.complex64, self.spec_shape(), out,
+        return self._call(self._lib.isht_forward, y, torch.complex64, self.spec_shape(), out,
                           torch.float32, self.grid_shape())
 
     def sht_T(self, gy, out=None):
         """Adjoint of ``sht`` (sht_backward)."""
-        return self._call(_lib.load().sht_backward, gy, torch.complex64, self.spec_shape(), out,
+        return self._call(self._lib.sht_backward, gy, torch.complex64, self.spec_shape(), out,
                           torch.float32, self.grid_shape())
 
     def isht_T(self, gx, out=None):
         """Adjoint of ``isht`` (isht_backward)."""
-        return self._call(_lib.load().isht_backward, gx, torch.float32, self.grid_shape(), out,
+        return self._call(self._lib.isht_backward, gx, torch.float32, self.grid_shape(), out,
                           torch.complex64, self.spec_shape())
 
     def mix(self, W, x, adjoint=False, out=None):
@@ -126,7 +132,7 @@ class Plan:
         if out is None:
             out = torch.empty(self.spec_shape(), dtype=torch.complex64, device=self.device)
         self._check(out, torch.complex64, self.spec_shape(), "output")
-        _lib.check(_lib.load().sht_channel_mix(self._h, ctypes.c_void_p(W.data_ptr()),
+        self._status(self._lib.sht_channel_mix(self._h, ctypes.c_void_p(W.data_ptr()),
                                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                                1 if adjoint else 0, _stream_ptr(self.device)))
         return out
@@ -141,7 +147,7 @@ class Plan:
         if out is None:
             out = torch.empty((d["lmax"], C, C), dtype=torch.complex64, device=self.device)
         self._check(out, torch.complex64, (d["lmax"], C, C), "dW")
-        _lib.check(_lib.load().sht_channel_mix_weight_grad(self._h, ctypes.c_void_p(g.data_ptr()),
+        self._status(self._lib.sht_channel_mix_weight_grad(self._h, ctypes.c_void_p(g.data_ptr()),
                                                            ctypes.c_void_p(x.data_ptr()),
                                                            ctypes.c_void_p(out.data_ptr()),
                                                            _stream_ptr(self.device)))
@@ -157,7 +163,7 @@ class Plan:
         if out is None:
             out = torch.empty(self.spec_shape(), dtype=torch.complex64, device=self.device)
         self._check(out, torch.complex64, self.spec_shape(), "output")
-        _lib.check(_lib.load().sht_isotropic_filter(self._h, ctypes.c_void_p(k.data_ptr()),
+        self._status(self._lib.sht_isotropic_filter(self._h, ctypes.c_void_p(k.data_ptr()),
                                                     ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                                     1 if adjoint else 0, _stream_ptr(self.device)))
         return out
@@ -171,7 +177,7 @@ class Plan:
         if out is None:
             out = torch.empty((C, d["lmax"]), dtype=torch.complex64, device=self.device)
         self._check(out, torch.complex64, (C, d["lmax"]), "dk")
-        _lib.check(_lib.load().sht_isotropic_filter_grad(self._h, ctypes.c_void_p(g.data_ptr()),
+        self._status(self._lib.sht_isotropic_filter_grad(self._h, ctypes.c_void_p(g.data_ptr()),
                                                          ctypes.c_void_p(x.data_ptr()),
                                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(self.device)))
         return out
@@ -186,7 +192,7 @@ class Plan:
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=self.device)
         self._check(out, torch.float32, shape, "out")
-        _lib.check(_lib.load().sht_psd(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        self._status(self._lib.sht_psd(self._h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        _stream_ptr(self.device)))
         return out
 
@@ -199,7 +205,7 @@ class Plan:
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=self.device)
         self._check(out, torch.float32, shape, "out")
-        _lib.check(_lib.load().sht_zonal_psd(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+        self._status(self._lib.sht_zonal_psd(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                              _stream_ptr(self.device)))
         return out
 
@@ -213,7 +219,7 @@ class Plan:
         self._check(obs, torch.complex64, (C, d["lmax"], d["mmax"]), "obs")
         loss = torch.empty(C, dtype=torch.float32, device=self.device)
         g = torch.empty_like(ens) if grad else None
-        _lib.check(_lib.load().sht_spectral_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
+        self._status(self._lib.sht_spectral_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
                                                  ctypes.c_void_p(obs.data_ptr()), 1 if fair else 0, int(l_hi),
                                                  ctypes.c_void_p(loss.data_ptr()),
                                                  ctypes.c_void_p(g.data_ptr() if grad else None),
@@ -228,7 +234,7 @@ class Plan:
         self._check(obs, torch.float32, (C, d["nlat"], d["nlon"]), "obs")
         loss = torch.empty(C, dtype=torch.float32, device=self.device)
         g = torch.empty_like(ens) if grad else None
-        _lib.check(_lib.load().sht_spatial_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
+        self._status(self._lib.sht_spatial_crps(self._h, ctypes.c_void_p(ens.data_ptr()),
                                                 ctypes.c_void_p(obs.data_ptr()), 1 if fair else 0,
                                                 ctypes.c_void_p(loss.data_ptr()),
                                                 ctypes.c_void_p(g.data_ptr() if grad else None),
@@ -241,18 +247,18 @@ class Plan:
         ms = -1.0 when the choice came from the cache file."""
         chosen, ms = ctypes.c_int(), ctypes.c_double()
         path = None if cache is None else str(cache).encode()
-        _lib.check(_lib.load().sht_plan_tune(self._h, path, ctypes.byref(chosen), ctypes.byref(ms)))
+        self._status(self._lib.sht_plan_tune(self._h, path, ctypes.byref(chosen), ctypes.byref(ms)))
         return chosen.value, ms.value
 
     def set_schedule(self, chunk=8, policy=0, ncb=2, staged=1):
         """Set the work schedule explicitly (results do not change)."""
-        _lib.check(_lib.load().sht_plan_set_schedule(self._h, int(chunk), int(policy), int(ncb), int(staged)))
+        self._status(self._lib.sht_plan_set_schedule(self._h, int(chunk), int(policy), int(ncb), int(staged)))
 
     def schedule(self):
         """(orders per chunk, XCD policy, field groups per workgroup, staged
         analysis output) in use."""
         c, p, n, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _lib.check(_lib.load().sht_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(n),
+        self._status(self._lib.sht_plan_get_schedule(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(n),
                                                      ctypes.byref(st)))
         return c.value, p.value, n.value, st.value
 
@@ -264,21 +270,21 @@ class Plan:
     # ------------------------------------------------------------ diagnostics
     def set_timing(self, enable):
         """Record HIP events around every kernel launch of later calls."""
-        _lib.check(_lib.load().sht_plan_timing(self._h, 1 if enable else 0))
+        self._status(self._lib.sht_plan_timing(self._h, 1 if enable else 0))
 
     def read_timing(self):
         """{kernel kind: (total ms, launches)} since the last read (synchronises)."""
         n = len(_lib.TIMING_KINDS)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_longlong * n)()
-        _lib.check(_lib.load().sht_plan_timing_read(self._h, ms, cnt, n))
+        self._status(self._lib.sht_plan_timing_read(self._h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.TIMING_KINDS)}
 
     # --------------------------------------------------------------- lifetime
     def close(self):
         """Free the plan (raises ShtError while graphs of the plan exist)."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            _lib.check(_lib.load().sht_plan_destroy(self._h))
+            self._status(self._lib.sht_plan_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -50,7 +50,15 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2507_12144_amd.build.build()")
-    lib = ctypes.CDLL(LIB_PATH)
+    _lib = open_library(LIB_PATH)
+    return _lib
+
+
+def open_library(path):
+    """A separately loaded copy of a build of the library (e.g. the
+    race-check build libsht_debug.so) with the C ABI's signatures declared;
+    its plans live in that copy only."""
+    lib = ctypes.CDLL(path)
     vp, ip, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
     lib.sht_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ShtDesc), ip, ip, vp]
     lib.sht_plan_destroy.argtypes = [vp]
@@ -85,7 +93,6 @@ def load():
     lib.sht_status_string.restype = ctypes.c_char_p
     lib.sht_last_error.argtypes = []
     lib.sht_last_error.restype = ctypes.c_char_p
-    _lib = lib
     return lib
 
 

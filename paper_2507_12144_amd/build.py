@@ -1,6 +1,7 @@
 """Build libsht.so (all HIP sources for gfx950) in-tree.
 
     python -m paper_2507_12144_amd.build        # or build() from Python
+    python -m paper_2507_12144_amd.build debug  # the race-check library
 
 Every source is compiled with hipcc for --offload-arch=gfx950 with packed
 float32 instructions disabled, then linked into the package directory.
@@ -32,9 +33,19 @@ def sources():
     return [os.path.join(CSRC, f) for f in sorted(names, key=order)]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+# Library variants: the release library and the race-check build (every
+# barrier drains all memory counters, every Legendre stage ends with a drain
+# and a barrier; see kernel_common.h), whose results must equal the
+# release library's bit for bit.
+VARIANTS = {
+    "release": (OUT, BUILD_DIR, []),
+    "debug": (os.path.join(PKG, "libsht_debug.so"), os.path.join(BUILD_DIR, "debug"), ["-DSHT_DEBUG_BARRIERS=1"]),
+}
+
+
+def _compile(src, build_dir, extra):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # hipcc's host pass warns that it does not know the packed-fp32 feature
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
@@ -43,22 +54,24 @@ def _compile(src):
     return obj, err
 
 
-def build(verbose=False):
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose=False, variant="release"):
+    out, build_dir, extra = VARIANTS[variant]
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: _compile(src, build_dir, extra), srcs))
     for obj, err in results:
         if verbose and err.strip():
             print(err, file=sys.stderr)
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    for v in (sys.argv[1:] or ["release"]):
+        print(build(verbose=True, variant=v))

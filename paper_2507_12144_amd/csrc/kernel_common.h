@@ -28,6 +28,30 @@ constexpr int vm_wait(int n) { return 0x0F70 | (n & 15) | (((n >> 4) & 3) << 14)
 // wave still reads a buffer the next copies overwrite.
 constexpr int vm_lds_wait(int n) { return vm_wait(n) & ~0x0F00; }
 
+// Race-check build (SHT_DEBUG_BARRIERS defined, libsht_debug.so): every
+// barrier below first drains all of the wave's memory counters, and every
+// stage of the Legendre kernels ends with a drain and a workgroup barrier,
+// so no copy, load or store of one stage overlaps another stage's work.  Its
+// results must equal the release build's bit for bit; a difference points
+// at a missing wait or barrier.
+#ifdef SHT_DEBUG_BARRIERS
+constexpr bool kDebugBarriers = true;
+#else
+constexpr bool kDebugBarriers = false;
+#endif
+
+__device__ __forceinline__ void debug_drain() {
+  if constexpr (kDebugBarriers) {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0);  // vmcnt, expcnt and lgkmcnt all zero
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  }
+}
+
+// End of one stage of a Legendre kernel: nothing in the release build.
+__device__ __forceinline__ void debug_stage_end() { debug_drain(); }
+
 // Workgroup barrier for LDS filled by asynchronous global->LDS copies.  The
 // caller first waits (vm_wait) for its own copies of the stage; the barrier
 // then makes every wave's copies visible.  The empty asm statements keep the
@@ -35,6 +59,7 @@ constexpr int vm_lds_wait(int n) { return vm_wait(n) & ~0x0F00; }
 // __syncthreads() no fence is emitted, so copies of later stages stay in
 // flight.
 __device__ __forceinline__ void stage_barrier() {
+  debug_drain();
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
@@ -49,6 +74,7 @@ namespace sht {
 // __syncthreads(), whose release fence also waits for every outstanding
 // global load and store (vmcnt(0)), it leaves prefetches in flight.
 __device__ __forceinline__ void lds_barrier() {
+  debug_drain();
   asm volatile("" ::: "memory");
   __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt unconstrained
   __builtin_amdgcn_s_barrier();

@@ -156,6 +156,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
         const float* xb = reinterpret_cast<const float*>(cur) + (4 * wave + lk) * 256 + li;
 #pragma unroll
         for (int r = 0; r < 16; ++r) xr[16 * u + r] = xb[16 * r];
+        debug_stage_end();
         return true;
       });
     } else {
@@ -209,6 +210,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
             acc = floatx4{0.f, 0.f, 0.f, 0.f};
           }
         }
+        debug_stage_end();
         return true;
       });
     }
@@ -343,6 +345,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
             acc[4 * t + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv, acc[4 * t + 3], 0, 0, 0);
           }
         }
+        debug_stage_end();
         return true;
       });
     }

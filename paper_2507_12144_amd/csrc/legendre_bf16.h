@@ -222,6 +222,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
       for (int r = 0; r < 16; ++r) v[r] = xb[16 * r];
       split8<ND>(v, xs[2 * u]);
       split8<ND>(v + 8, xs[2 * u + 1]);
+      debug_stage_end();
       return true;
     });
     floatx4 main = {0.f, 0.f, 0.f, 0.f}, corr = main;
@@ -269,6 +270,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
             corr = main;
           }
         }
+        debug_stage_end();
         return true;
       });
     }
@@ -390,6 +392,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
             products<NP, ND>(av, bv, acc[part * SS + s], acc[part * SS + s]);
           }
         }
+        debug_stage_end();
         return true;
       });
     }

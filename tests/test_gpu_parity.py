@@ -784,3 +784,62 @@ def test_environment_switches(pkg, tmp_path):
             os.environ.pop(k, None)
     assert cache.exists() and len(cache.read_text().splitlines()) == 1
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x2", "bf16x3"])
+def test_race_check_build_bitwise_equal(pkg, prec):
+    """The race-check build libsht_debug.so (every barrier drains all memory
+    counters and every Legendre stage ends with a drain and a workgroup
+    barrier, so no copy, load or store of one stage overlaps another stage's
+    work) gives the release library's outputs bit for bit: all four
+    transforms, direct and staged spectra, a multi-segment plan with every
+    ring padding, odd mmax and mmax < lmax, and the scores and mix kernels
+    that use the same barriers."""
+    path = os.path.join(os.path.dirname(pkg.__file__), "libsht_debug.so")
+    assert os.path.exists(path), "libsht_debug.so is not built: python -m paper_2507_12144_amd.build debug"
+    shapes = [(33, 64, 17, 17, 0, 1, 3), (65, 128, 64, 41, 0, 2, 3), (181, 360, 180, 180, 0, 1, 5),
+              (90, 180, 90, 90, 1, 1, 20), (361, 720, 360, 360, 0, 1, 9)]
+    _say("race-check build", prec)
+    debug = pkg._lib.open_library(path)
+    plans = [_multi_plan(pkg, shapes, prec),
+             pkg.Plan([dict(nlat=s[0], nlon=s[1], lmax=s[2], mmax=s[3], grid=s[4], batch=s[5], channels=s[6])
+                       for s in shapes], precision=prec, library=debug)]
+    u_h, _, _ = _batched_io(pkg, plans[0], shapes, seed=51)
+    u = _to_dev(u_h, torch.float32)
+    a_h = np.zeros(plans[0].spec_elems, np.complex64)
+    for i, (nlat, nlon, lmax, mmax, grid, B, C) in enumerate(shapes):
+        _, so = plans[0].segment(i)
+        ai = synth.coefficients(52 + i, B, C, lmax, mmax).astype(np.complex64)
+        a_h[so:so + ai.size] = ai.ravel()
+    a = _to_dev(a_h, torch.complex64)
+    smask, gmask = _segment_mask(plans[0], shapes, True), _segment_mask(plans[0], shapes, False)
+    outs = []
+    for plan in plans:
+        res = []
+        for staged in (0, 3):
+            plan.set_schedule(8, 0, 2, staged)
+            res += [plan.sht(u).cpu().numpy()[smask], plan.isht_T(u).cpu().numpy()[smask],
+                    plan.isht(a).cpu().numpy()[gmask], plan.sht_T(a).cpu().numpy()[gmask]]
+        outs.append(res)
+    for i, (d, r) in enumerate(zip(outs[1], outs[0])):
+        assert np.array_equal(d, r), i
+    for plan in plans:
+        plan.close()
+    if prec != "fp32":
+        return
+    # single-segment plans: the channel mix, its weight gradient and the
+    # spectral CRPS with gradient (LDS-staged GEMM tiles and block sums)
+    B, C, L = 2, 48, 40
+    desc = dict(nlat=42, nlon=80, lmax=L, mmax=L, grid="gauss", batch=B, channels=C)
+    p0, p1 = pkg.Plan(desc), pkg.Plan(desc, library=debug)
+    g = torch.Generator(device="cuda").manual_seed(53)
+    x = torch.randn((B, C, L, L), device="cuda", dtype=torch.complex64, generator=g)
+    W = torch.randn((L, C, C), device="cuda", dtype=torch.complex64, generator=g)
+    for f in (lambda p: p.mix(W, x), lambda p: p.mix(W, x, adjoint=True), lambda p: p.mix_weight_grad(x, x)):
+        assert torch.equal(f(p0), f(p1))
+    obs = x[0]
+    l0, g0 = p0.spectral_crps(x, obs, grad=True)
+    l1, g1 = p1.spectral_crps(x, obs, grad=True)
+    assert torch.equal(l0, l1) and torch.equal(g0, g1)
+    p0.close()
+    p1.close()
