@@ -2,6 +2,7 @@
 
     python -m paper_2507_12144_amd.build        # or build() from Python
     python -m paper_2507_12144_amd.build debug  # the race-check library
+    python -m paper_2507_12144_amd.build asan   # host-sanitizer test build
 
 Every source is compiled with hipcc for --offload-arch=gfx950 with packed
 float32 instructions disabled, then linked into the package directory.
@@ -72,6 +73,49 @@ def build(verbose=False, variant="release"):
     return out
 
 
+ROOT = os.path.dirname(PKG)
+ASAN_DIR = os.path.join(ROOT, "tests", "asan")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_host_asan():
+    """Host-sanitizer test build in tests/asan: the library's host logic
+    (api.hip) compiled with AddressSanitizer on the host pass only (device
+    code unchanged), linked with the release objects of the other sources
+    (run build() first) into libsht_asan.so, and the C driver abi_driver.c
+    built against it.  The sanitizer is never applied to GPU code."""
+    out_dir = os.path.join(BUILD_DIR, "asan")
+    os.makedirs(out_dir, exist_ok=True)
+    api = os.path.join(CSRC, "api.hip")
+    others = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in sources() if s != api]
+    missing = [o for o in others if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"release objects missing ({os.path.basename(missing[0])}): run build() first")
+    obj = os.path.join(out_dir, "api.hip.o")
+    host_asan = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+    r = subprocess.run([HIPCC] + FLAGS + host_asan + ["-c", api, "-o", obj], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (host sanitizer) failed:\n{r.stderr}")
+    clangxx = os.path.join(ROCM, "llvm", "bin", "clang++")
+    clang = os.path.join(ROCM, "llvm", "bin", "clang")
+    lib = os.path.join(ASAN_DIR, "libsht_asan.so")
+    link = [clangxx, "-shared", "-fPIC", "-fsanitize=address", "-o", lib, obj] + others + [
+        "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (host sanitizer) failed:\n{r.stderr}")
+    drv = os.path.join(ASAN_DIR, "abi_driver")
+    cc = [clang, "-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__",
+          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(ROCM, "include"),
+          "-o", drv, os.path.join(ASAN_DIR, "abi_driver.c"), "-L" + ASAN_DIR, "-lsht_asan",
+          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cc, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"driver build (host sanitizer) failed:\n{r.stderr}")
+    return drv
+
+
 if __name__ == "__main__":
     for v in (sys.argv[1:] or ["release"]):
-        print(build(verbose=True, variant=v))
+        print(build_host_asan() if v == "asan" else build(verbose=True, variant=v))
