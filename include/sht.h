@@ -328,10 +328,11 @@ sht_status sht_graph_destroy(sht_graph_t graph);
  * or 4; the bf16 forms always take 2),
  * the orders per scheduling chunk of the Legendre work list (4, 8, 16, 32)
  * and how chunks are dealt to the 8 XCDs (largest-first to the least-loaded
- * XCD, or round robin).  sht_plan_tune times one SHT -> ISHT -> ISHT^T ->
- * SHT^T pass per candidate (after one warm-up pass) on library-allocated
- * synthetic buffers, requires every candidate's four outputs to equal the
- * default candidate's bit for bit (parity), keeps the fastest, and returns
+ * XCD, or round robin).  sht_plan_tune times SHT -> ISHT -> ISHT^T -> SHT^T
+ * passes per candidate (the fastest of five, after one warm-up pass) on
+ * library-allocated synthetic buffers, requires every candidate's four
+ * outputs to equal the default candidate's bit for bit (parity), keeps the
+ * fastest (a candidate must beat the one kept by 1 %), and returns
  * its index in *chosen and its time in *best_ms (either may be NULL).  With
  * cache_path != NULL the choice is looked up first in that text file under a
  * key of (gfx arch, descriptors, precision, candidate-list version) and
