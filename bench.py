@@ -60,6 +60,8 @@ def parse():
                     help="sht721: skip the graph replay and the peak microbenchmarks after the timed region, so "
                          "that a profiler sees only the plan build, the warm-up and the timed steps")
     ap.add_argument("--block-channels", type=int, default=256, help="sfno_block: channels (677 in the model)")
+    ap.add_argument("--replays", type=int, default=1000, help="batched: timed graph replays (p50 / p99 over them)")
+    ap.add_argument("--replay-warmup", type=int, default=50, help="batched: untimed replays first")
     return ap.parse_args()
 
 
@@ -148,7 +150,8 @@ BATCHED_SEGMENTS = [  # nlat, nlon, lmax, members
 def batched_bench(args):
     """One plan over the three grids; the fwd+bwd chain SHT -> ISHT -> ISHT^T
     -> SHT^T over all 16 x 72 fields captured as one HIP graph after the
-    schedule autotuner ran; each replay timed with HIP events."""
+    schedule autotuner ran; --replays timed replays (default 1000) after
+    --replay-warmup untimed ones (default 50), each timed with HIP events."""
     import numpy as np
     import torch
     import paper_2507_12144_amd as P
@@ -172,10 +175,11 @@ def batched_bench(args):
     gy, gx = torch.empty_like(y), torch.empty_like(x)
     graph = plan.graph([("sht", u, y), ("isht", y, x), ("isht_T", x, gy), ("sht_T", gy, gx)])
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    n, warm = args.replays, args.replay_warmup
+    for _ in range(warm):
         graph.launch()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
     t0 = time.perf_counter()
     for a, b in evs:
         a.record(stream)
@@ -186,8 +190,8 @@ def batched_bench(args):
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     out = {
         "metric": "batched uneven-grid SHT+ISHT fwd+bwd fields/sec (one plan, graph replay); p50/p99 replay latency",
-        "value": round(fields * args.steps / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "value": round(fields * n / wall, 1), "unit": "fields/s", "n_gpus": 1, "steps": n,
+        "warmup": warm, "ms_per_step": round(wall * 1e3 / n, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else args.precision,
         "data": "synthetic",
         "config": {"workload": "16 ensemble members x 72 channels over equiangular 181x360 (L180), 361x720 "
