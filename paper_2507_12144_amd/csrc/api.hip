@@ -250,6 +250,7 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   g.kpad = legendre_ring_pad(g.nk);
   g.groups = (g.F + 7) / 8;
   if (g.kpad < 0) return fail(SHT_ERR_UNSUPPORTED, "nlat = %d: more than %d northern rings", d.nlat, kMaxRings);
+  g.wslab = static_cast<long long>(g.groups) * g.kpad * 16 + kWorkPad;
   if (!make_dft_plan(d.nlon, &S.dp)) return fail(SHT_ERR_UNSUPPORTED, "nlon = %d cannot be factored", d.nlon);
 
   hipError_t e;
@@ -331,7 +332,7 @@ sht_status build_segment(Segment& S, const sht_desc& d, Storage storage, hipStre
   }
 
   // workspace W[m][p][g][k][16]; rings k >= nk stay zero forever
-  const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.groups * g.kpad * 16 * sizeof(float);
+  const size_t wbytes = static_cast<size_t>(d.mmax) * 2 * g.wslab * sizeof(float);
   e = dev_alloc(reinterpret_cast<void**>(&S.work), wbytes);
   if (e != hipSuccess) return hip_fail(e, "workspace allocation");
   e = hipMemsetAsync(S.work, 0, wbytes, st);

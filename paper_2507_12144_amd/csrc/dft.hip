@@ -30,6 +30,7 @@ constexpr int NT = 512;    // threads per workgroup
 
 struct DftArgs {
   int nlat, nlon, lmax, mmax, nk, F, kpad, G;
+  long long wslab;         // floats per (m, parity) slab of W
   int nitems;              // G * nk * 2 workgroup items
   int nstages;
   const int* radix;        // the segment's radix plan (device memory)
@@ -364,7 +365,7 @@ __device__ __forceinline__ Item item_of(const DftArgs& a, int local) {
 }
 
 __device__ __forceinline__ size_t wrow(const DftArgs& a, int m, int p, int g, int kk) {
-  return ((static_cast<size_t>(2 * m + p) * a.G + g) * a.kpad + kk) * 16;
+  return static_cast<size_t>(2 * m + p) * a.wslab + (static_cast<size_t>(g) * a.kpad + kk) * 16;
 }
 
 template <class FFT>
@@ -608,6 +609,7 @@ __device__ __forceinline__ DftArgs seg_args(const SegDev& sd, float c_rest) {
   a.F = sd.g.F;
   a.kpad = sd.g.kpad;
   a.G = sd.g.groups;
+  a.wslab = sd.g.wslab;
   a.nitems = sd.dft_items;
   a.nstages = sd.nstages;
   a.radix = sd.radix;

@@ -18,12 +18,21 @@ constexpr int kMaxRadices = 16;
 enum class Storage : int { F32 = 0, BF16 = 1, BF16X2 = 2, BF16X3 = 3 };
 
 // Geometry of one segment as the kernels see it.
+// Padding after every (m, parity) slab of the workspace W (floats).  The
+// ring DFTs write and read W at a stride of one slab pair per order m; an
+// unpadded slab is a multiple of 16 KiB (kpad * 64 bytes per field group),
+// so the 64 orders of a wave would all fall on the same offset modulo
+// 16 KiB.  256 bytes of padding spread them.
+constexpr long long kWorkPad = 64;
+
 struct SegGeom {
   int nlat, nlon, lmax, mmax;
   int F;          // fields = batch * channels
   int nk;         // northern rings incl. the equator: (nlat + 1) / 2
   int kpad;       // nk rounded up to a ring count the contraction kernels hold
   int groups;     // field groups of 8: ceil(F / 8)
+  long long wslab;  // floats of one (m, parity) slab of the workspace W:
+                    // groups * kpad * 16 plus kWorkPad
   bool has_equator;  // nlat odd
 };
 

@@ -114,7 +114,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
   float xr[KS];
   // this wave's K slice: S or A of its parity and field group (idle waves,
   // past the last field group, read group 0 and never use it)
-  const float* Wg = W + (static_cast<size_t>(2 * m + p) * g.groups + (active ? cb : 0)) * KPAD * 16;
+  const float* Wg = W + static_cast<size_t>(2 * m + p) * g.wslab + static_cast<size_t>(active ? cb : 0) * KPAD * 16;
   if constexpr (!S::XSTREAM) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) xr[s] = Wg[(lk * KS + s) * 16 + li];
@@ -352,7 +352,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
     __builtin_amdgcn_s_waitcnt(vm_wait(0));
   }
   if (!active) return;
-  float* Wp = W + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16;
+  float* Wp = W + static_cast<size_t>(2 * m + p) * g.wslab + static_cast<size_t>(cb) * KPAD * 16;
   // acc[4t + q][r] is output row 4 lk + r, ring k = (4 lk + r) * KR + 4 t + q
 #pragma unroll
   for (int t = 0; t < TS; ++t)

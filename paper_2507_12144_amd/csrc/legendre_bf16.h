@@ -187,7 +187,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   const int nbp = (np + 15) >> 4;
   const int nst = PARTS * nb;
   const uint16_t* tab = static_cast<const uint16_t*>(sd.tab_ana) + sd.tab_off[m];
-  const float* Wg = sd.work + (static_cast<size_t>(2 * m + p) * g.groups + (active ? cb : 0)) * KPAD * 16;
+  const float* Wg =
+      sd.work + static_cast<size_t>(2 * m + p) * g.wslab + static_cast<size_t>(active ? cb : 0) * KPAD * 16;
   const float ms = (m == 0) ? 1.f : c_rest;
   float* yf = reinterpret_cast<float*>(y);
   const int f = 8 * cb + (li >> 1);
@@ -399,7 +400,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
     __builtin_amdgcn_s_waitcnt(vm_wait(0));
   }
   if (!active) return;
-  float* Wp = sd.work + (static_cast<size_t>(2 * m + p) * g.groups + cb) * KPAD * 16;
+  float* Wp = sd.work + static_cast<size_t>(2 * m + p) * g.wslab + static_cast<size_t>(cb) * KPAD * 16;
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb)
 #pragma unroll
