@@ -421,13 +421,13 @@ def main():
         return
     if args.workload in ("batched", "sfno_block", "scores", "noise"):
         if args.gpus != 1:
-            print("bench.py: this build measures one GPU only", file=sys.stderr, flush=True)
+            print("bench.py measures one GPU only", file=sys.stderr, flush=True)
             sys.exit(2)
         {"batched": batched_bench, "sfno_block": sfno_block_bench, "scores": scores_bench,
          "noise": noise_bench}[args.workload](args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
               "fields are independent, so N GPUs would each run this single-GPU workload.", file=sys.stderr)
         sys.exit(2)
 
