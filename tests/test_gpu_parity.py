@@ -645,12 +645,15 @@ def _segment_mask(plan, shapes, spectral):
     return mask
 
 
-def test_graph_replay_matches_eager(pkg):
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_graph_replay_matches_eager(pkg, prec):
     """The fwd+bwd chain SHT -> ISHT -> ISHT^T -> SHT^T captured as one HIP
     graph; several replays, with eager work and synchronisation between them,
-    each equal bit for bit to the eager chain."""
-    _say("graph replay over", GRAPH_SEGS)
-    plan = _multi_plan(pkg, GRAPH_SEGS)
+    each equal bit for bit to the eager chain (float32: staged analysis
+    output, the spectrum transpose in the graph; split bf16: both directions
+    staged, the staging kernel in the graph too)."""
+    _say("graph replay over", GRAPH_SEGS, prec)
+    plan = _multi_plan(pkg, GRAPH_SEGS, prec)
     u_h, _, _ = _batched_io(pkg, plan, GRAPH_SEGS, seed=5)
     u = _to_dev(u_h, torch.float32)
     y = plan.sht(u)
