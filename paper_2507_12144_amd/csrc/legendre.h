@@ -92,9 +92,9 @@ __device__ __forceinline__ void issue_stage(v4f* B, const float* __restrict__ ta
 
 // Analysis.  Contraction index k of a wave's K slice = lk * KS + 4t + q for
 // lane group lk, piece t of the row block and component q.
-template <int NCB, int KS>
+template <int NCB, int KS, bool STG>
 __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, const float* __restrict__ W,
-                                              float2* __restrict__ y, float c_rest, int staged, v4f* b0, v4f* b1,
+                                              float2* __restrict__ y, float c_rest, v4f* b0, v4f* b1,
                                               v4f* b2) {
   using S = Stages<NCB, KS>;
   constexpr int SC = S::SC, NW = S::NW, LPW = S::LPW, NTH = S::NTH, PARTS = S::PARTS, T4 = S::T4;
@@ -187,7 +187,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, xr[kb + 4 * t + 3], acc, 0, 0, 0);
           }
           if constexpr (part == PARTS - 1) {
-            if (staged & 1) {
+            if constexpr (STG) {
               // the 16 x 16 tile, contiguous, into the order-major staging
               // buffer (rows past the parity's last degree hold zeros)
               float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
   // degree l = m for its fields, y[f][m][m+1 .. mmax-1], one contiguous run
   // per field, instead of the scattered column y[f][0 .. m-1][m].  (Staged:
   // the transpose writes them.)
-  if (!(staged & 1) && m < g.lmax) {
+  if (!STG && m < g.lmax) {
     const int fbeg = 8 * NCB * c;
     const int fend = min(g.F, fbeg + 8 * NCB);
     const int run = g.mmax - 1 - m;
@@ -384,12 +384,21 @@ __global__ __launch_bounds__(128 * NCB) __attribute__((amdgpu_waves_per_eu(3))) 
   const SegDev& sd = segs[wk.y >> 16];
   const int m = wk.x, c = wk.y & 0xffff;
   float2* ys = y + sd.spec_off;
+  // the output path is a compile-time choice (as in the synthesis): with a
+  // run-time branch the compiler spilled the scaled results around it
+  auto body = [&](auto ks_c) {
+    constexpr int KS = decltype(ks_c)::value;
+    if (staged & 1)
+      analysis_body<NCB, KS, true>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2);
+    else
+      analysis_body<NCB, KS, false>(sd, m, c, sd.work, ys, c_rest, b0, b1, b2);
+  };
   switch (sd.g.kpad) {
-    case 64: analysis_body<NCB, 16>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
-    case 128: analysis_body<NCB, 32>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
-    case 192: analysis_body<NCB, 48>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
-    case 256: analysis_body<NCB, 64>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
-    default: analysis_body<NCB, 96>(sd, m, c, sd.work, ys, c_rest, staged, b0, b1, b2); break;
+    case 64: body(std::integral_constant<int, 16>{}); break;
+    case 128: body(std::integral_constant<int, 32>{}); break;
+    case 192: body(std::integral_constant<int, 48>{}); break;
+    case 256: body(std::integral_constant<int, 64>{}); break;
+    default: body(std::integral_constant<int, 96>{}); break;
   }
 }
 
