@@ -19,6 +19,15 @@ __device__ __forceinline__ int2 take_work(const int2* __restrict__ work, int per
 
 namespace sht {
 
+// Global-memory (address space 1) views of generic pointers: accesses
+// through them compile to global_* instead of flat_* instructions.  A flat
+// store may address LDS, so while global->LDS copies are in flight the
+// compiler makes it wait for all of them; a global store needs no such wait.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) v2f_t gfloat2;
+__device__ __forceinline__ gfloat* as_global(float* p) { return (gfloat*)p; }
+
 // s_waitcnt immediate that waits until at most n vector-memory operations of
 // this wave are outstanding (expcnt and lgkmcnt left at their maxima).
 constexpr int vm_wait(int n) { return 0x0F70 | (n & 15) | (((n >> 4) & 3) << 14); }

@@ -120,9 +120,14 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
     for (int s = 0; s < KS; ++s) xr[s] = Wg[(lk * KS + s) * 16 + li];
   }
   const float ms = (m == 0) ? 1.f : c_rest;
-  float* yf = reinterpret_cast<float*>(y);
+  gfloat* yf = as_global(reinterpret_cast<float*>(y));
   const int f = 8 * cb + (li >> 1);
   const bool fok = active && f < g.F;
+  // this wave's staging tiles, addressed before the pipeline starts: read
+  // inside it, the offset would be reloaded after every stage barrier (a
+  // global load whose wait also drains the table copies in flight)
+  gfloat* const ystg_out =
+      as_global(sd.ystage + sd.ystage_off[m] + (static_cast<size_t>(p) * g.groups + (active ? cb : 0)) * nb * 256);
   if (nb > 0) {
     // Every stage issues the copies of stage s+2, past the end too, so that
     // each wave always has exactly LPW copies in flight behind the ones it
@@ -190,7 +195,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
             if constexpr (STG) {
               // the 16 x 16 tile, contiguous, into the order-major staging
               // buffer (rows past the parity's last degree hold zeros)
-              float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
+              gfloat* dst = ystg_out + static_cast<size_t>(ib) * 256;
 #pragma unroll
               for (int r = 0; r < 4; ++r) dst[(4 * lk + r) * 16 + li] = acc[r] * ms;
             } else {
@@ -202,8 +207,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
                 const int i = 16 * ib + 4 * lk + r;
                 if (fok && (li & 1) == 0 && i < np) {
                   const int l = m + p + 2 * i;
-                  *reinterpret_cast<float2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
-                      make_float2(acc[r] * ms, other * ms);
+                  *reinterpret_cast<gfloat2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
+                      v2f_t{acc[r] * ms, other * ms};
                 }
               }
             }

@@ -190,9 +190,14 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   const float* Wg =
       sd.work + static_cast<size_t>(2 * m + p) * g.wslab + static_cast<size_t>(active ? cb : 0) * KPAD * 16;
   const float ms = (m == 0) ? 1.f : c_rest;
-  float* yf = reinterpret_cast<float*>(y);
+  gfloat* yf = as_global(reinterpret_cast<float*>(y));
   const int f = 8 * cb + (li >> 1);
   const bool fok = active && f < g.F;
+  // this wave's staging tiles, addressed before the pipeline starts: read
+  // inside it, the offset would be reloaded after every stage barrier (a
+  // global load whose wait also drains the table copies in flight)
+  gfloat* const ystg_out =
+      as_global(sd.ystage + sd.ystage_off[m] + (static_cast<size_t>(p) * g.groups + (active ? cb : 0)) * nb * 256);
   if (nb > 0) {
     constexpr int ND = data_planes(NP);
     bf16x8 xs[T8][ND];
@@ -249,7 +254,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
           if constexpr (part == PARTS - 1) {
             if (staged & 1) {
               // the 16 x 16 tile, contiguous, into the order-major staging buffer
-              float* dst = sd.ystage + sd.ystage_off[m] + ((static_cast<size_t>(p) * g.groups + cb) * nb + ib) * 256;
+              gfloat* dst = ystg_out + static_cast<size_t>(ib) * 256;
 #pragma unroll
               for (int r = 0; r < 4; ++r) dst[(4 * lk + r) * 16 + li] = (main[r] + corr[r]) * ms;
             } else {
@@ -262,8 +267,8 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
                 const int i = 16 * ib + 4 * lk + r;
                 if (fok && (li & 1) == 0 && i < np) {
                   const int l = m + p + 2 * i;
-                  *reinterpret_cast<float2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
-                      make_float2(v * ms, other * ms);
+                  *reinterpret_cast<gfloat2*>(yf + ((static_cast<size_t>(f) * g.lmax + l) * g.mmax + m) * 2) =
+                      v2f_t{v * ms, other * ms};
                 }
               }
             }
