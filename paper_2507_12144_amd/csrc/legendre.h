@@ -305,17 +305,22 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
   if (nb > 0) {
     // Stage u issues the table copies of stage u+2 and, at part 1, the
-    // spectrum copies of the next row block (4 per wave).  Behind the table
-    // copies of stage s come those of stage s+1 and the spectrum copies of
-    // stages s-2 and s-1 if at part 1; at part 0 the spectrum copies of part
-    // 1 of the previous row block must be complete too, and only the table
-    // copies of the PARTS-2 stages in between follow them.  The prologue
-    // plays stages -2 and -1 the same way.
+    // spectrum copies of the next row block (4 per wave): with two parts
+    // before the table copies (part 0, right after, then waits for all but
+    // one stage's copies instead of all of them), with three after them (the
+    // gathered spectrum then does not hold up the table copies).  Behind the
+    // table copies of stage s (issued at stage s-2) come those of stage s+1,
+    // the spectrum copies of stage s-1 if at part 1, and, issued after, those
+    // of stage s-2 if at part 1.  At part 0 the spectrum copies of part 1 of
+    // the previous row block must be complete too: only the table copies of
+    // the PARTS-2 stages after it, and of that stage itself if issued after,
+    // follow them.  The prologue plays stages -2 and -1 the same way (stage
+    // -2 is at part 1 with three parts, stage -1 with two).
     static_assert(PARTS == 2 || PARTS == 3, "spectrum refill at part 1");
+    constexpr bool SF = PARTS == 2;  // spectrum copies first at part 1
     issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
-    if constexpr (PARTS == 3) spec_copy(0);  // stage -2 is at part 1
+    spec_copy(0);
     issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
-    if constexpr (PARTS == 2) spec_copy(0);  // stage -1 is at part 1
     float bc[4];
     for (int st0 = 0; st0 < nst; st0 += S::NST) {
       unrolled<0, S::NST>([&](auto su_c) {
@@ -326,8 +331,9 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         v4f* cur = ring_buf<su>(b0, b1, b2);
         v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
         constexpr int pm2 = (part + 2 * PARTS - 2) % PARTS, pm1 = (part + PARTS - 1) % PARTS;
-        constexpr int behind = LPW + (pm2 == 1 ? 4 : 0) + (pm1 == 1 ? 4 : 0);
-        constexpr int need = (part == 0 && (PARTS - 2) * LPW < behind) ? (PARTS - 2) * LPW : behind;
+        constexpr int behind = LPW + (pm1 == 1 ? 4 : 0) + (!SF && pm2 == 1 ? 4 : 0);
+        constexpr int spec_behind = (SF ? PARTS - 1 : PARTS - 2) * LPW;
+        constexpr int need = (part == 0 && spec_behind < behind) ? spec_behind : behind;
         __builtin_amdgcn_s_waitcnt(vm_lds_wait(need));
         stage_barrier();
         const int ib = st / PARTS;
@@ -335,8 +341,9 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
 #pragma unroll
           for (int q = 0; q < 4; ++q) bc[q] = wspec[64 * q + lane];
         }
+        if constexpr (SF && part == 1) spec_copy(ib + 1);
         issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
-        if constexpr (part == 1) spec_copy(ib + 1);
+        if constexpr (!SF && part == 1) spec_copy(ib + 1);
         if (active && ib < nbp) {
 #pragma unroll
           for (int tt = 0; tt < SC; ++tt) {

@@ -144,19 +144,28 @@ constexpr int x_behind(int gs) {
   return n;
 }
 
-// Synthesis: copies in flight that stage s may leave outstanding.  Stage j
-// issues the table copies of stage j+D and, at part 1, the NB spectrum
-// copies of the next row block.  Behind the table copies of stage s come
-// those of stages s+1 .. s+D-1 and the spectrum copies of every stage
-// s-D .. s-1 at part 1; a stage at part 0 also needs the spectrum copies
-// issued at part 1 of the previous row block, which only the table copies
-// of the PARTS-2 stages in between follow.
+// Synthesis: stage j issues the table copies of stage j+D and, at part 1,
+// the NB spectrum copies of the next row block: before the table copies when
+// a row block has two parts (part 0, right after, then waits for all but
+// one stage's copies instead of all of them), after them otherwise (the
+// gathered spectrum then does not hold up the table copies).
+constexpr bool spec_first(int parts) { return parts == 2; }
+
+// Copies in flight that synthesis stage s may leave outstanding.  Behind the
+// table copies of stage s (issued at stage s-D) come those of stages s+1 ..
+// s+D-1 and the spectrum copies of the stages at part 1 among s-D+1 .. s-1,
+// and among s-D too if issued after the table copies; a stage at part 0
+// also needs the spectrum copies issued at part 1 of the previous row block,
+// which only the table copies of the PARTS-2 stages after that stage, and
+// of that stage itself if issued after, follow.
 template <int PARTS, int LPW, int D, int NB>
 constexpr int s_behind(int s) {
+  constexpr bool sf = spec_first(PARTS);
   int n = (D - 1) * LPW;
-  for (int j = s - D; j < s; ++j)
+  for (int j = sf ? s - D + 1 : s - D; j < s; ++j)
     if (((j % PARTS) + PARTS) % PARTS == 1) n += NB;
-  if (s % PARTS == 0 && (PARTS - 2) * LPW < n) n = (PARTS - 2) * LPW;
+  const int ns = (sf ? PARTS - 1 : PARTS - 2) * LPW;
+  if (s % PARTS == 0 && ns < n) n = ns;
   return n;
 }
 
@@ -165,9 +174,9 @@ constexpr int s_behind(int s) {
 // lane group lk, step t (K = 32: 8 values a lane) and element e.  Global
 // stage g < XS brings rings 16g .. 16g+15 of every lane group's K slice of
 // S or A (each wave its own four pieces); stage XS + s is table stage s.
-template <int KS, int NP, int NBUF>
+template <int KS, int NP, int NBUF, bool STG>
 __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, float2* __restrict__ y, float c_rest,
-                                              int staged, v4f* ring) {
+                                              v4f* ring) {
   constexpr int T8 = KS / 8;  // steps per 16-row block
   using G = Geo<T8, NP, KS / 4, NBUF>;
   constexpr int SC = G::SC, SS = G::SS, LPW = G::LPW, PARTS = G::PARTS;
@@ -252,7 +261,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
             products<NP, ND>(av, xs[part * SS + s], main, corr);
           }
           if constexpr (part == PARTS - 1) {
-            if (staged & 1) {
+            if constexpr (STG) {
               // the 16 x 16 tile, contiguous, into the order-major staging buffer
               gfloat* dst = ystg_out + static_cast<size_t>(ib) * 256;
 #pragma unroll
@@ -286,7 +295,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
   // zeros of the spectrum: degree l = m, orders m+1 .. mmax-1 of this
   // chunk's fields (contiguous runs; the orders together cover every l < m';
   // staged: the transpose writes them)
-  if (!(staged & 1) && m < g.lmax) {
+  if (!STG && m < g.lmax) {
     const int fbeg = 16 * c;
     const int fend = min(g.F, fbeg + 16);
     const int run = g.mmax - 1 - m;
@@ -303,9 +312,9 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
 // 4-byte global->LDS copies into one slot of 2 KiB per wave (value e of
 // lane l at float 64 e + l): all loads in flight are LDS copies, so every
 // wait is one of the counted waits below.
-template <int KS, int NP, int NBUF>
+template <int KS, int NP, int NBUF, bool STG>
 __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, const float2* __restrict__ y,
-                                               int staged, v4f* ring, float* spec) {
+                                               v4f* ring, float* spec) {
   constexpr int KPAD = 4 * KS;
   constexpr int KR = KPAD / 16;  // steps (16-ring output blocks) per 32-row block
   using G = Geo<KR, NP, KS / 8, NBUF, 2>;
@@ -343,7 +352,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
       const int i = 32 * ib + 8 * lk + e;
-      if (staged & 2) {
+      if constexpr (STG) {
         const bool in = i < np;
         const float* src = ystg + ((static_cast<size_t>(in ? p : 0) * g.groups + cbs) * nbs) * 256 +
                            static_cast<size_t>(in ? i : 0) * 16 + li;
@@ -359,14 +368,18 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
 #pragma unroll
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
   if (nb32 > 0) {
-    // The prologue plays stages -D .. -1 as the loop does (table copies of
-    // stage v+D, then the spectrum of row block 0 where v is at part 1);
-    // when none of them is at part 1, row block 0's spectrum goes first.
+    // The prologue plays stages -D .. -1 as the loop does (the table copies
+    // of stage v+D and the spectrum of row block 0 where v is at part 1, in
+    // the loop's order); when none of them is at part 1, row block 0's
+    // spectrum goes first.
+    constexpr bool SF = spec_first(PARTS);
     if constexpr (PARTS > D + 1) spec_copy(0);
     unrolled<0, D>([&](auto i_c) {
       constexpr int i = decltype(i_c)::value;
+      constexpr bool at1 = (((i - D) % PARTS) + PARTS) % PARTS == 1;
+      if constexpr (SF && at1) spec_copy(0);
       issue_stage<SC, LPW, PARTS>(rbuf<i, NBUF>(ring), tab, nb32, nb32, KR * NP, i, wave, lane);
-      if constexpr ((((i - D) % PARTS) + PARTS) % PARTS == 1) spec_copy(0);
+      if constexpr (!SF && at1) spec_copy(0);
       return true;
     });
     constexpr int ND = data_planes(NP);
@@ -386,8 +399,9 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
           for (int e = 0; e < NB; ++e) bn[e] = wspec[64 * e + lane];
           split8<ND>(bn, bv);
         }
+        if constexpr (SF && part == 1) spec_copy(ib + 1);
         issue_stage<SC, LPW, PARTS>(rbuf<su + D, NBUF>(ring), tab, nb32, nb32, KR * NP, st + D, wave, lane);
-        if constexpr (part == 1) spec_copy(ib + 1);
+        if constexpr (!SF && part == 1) spec_copy(ib + 1);
         const v4f* cur = rbuf<su, NBUF>(ring);
         if (active && ib < nbp) {
 #pragma unroll
@@ -432,12 +446,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void a
   const int m = wk.x, c = wk.y & 0xffff;
   float2* ys = y + sd.spec_off;
   constexpr int R = kRingBuffers;
+  // the output path is a compile-time choice, as in the float32 kernels
+  auto body = [&](auto ks_c) {
+    constexpr int KS = decltype(ks_c)::value;
+    if (staged & 1)
+      analysis_body<KS, NP, R, true>(sd, m, c, ys, c_rest, ring);
+    else
+      analysis_body<KS, NP, R, false>(sd, m, c, ys, c_rest, ring);
+  };
   switch (sd.g.kpad) {
-    case 64: analysis_body<16, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
-    case 128: analysis_body<32, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
-    case 192: analysis_body<48, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
-    case 256: analysis_body<64, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
-    default: analysis_body<96, NP, R>(sd, m, c, ys, c_rest, staged, ring); break;
+    case 64: body(std::integral_constant<int, 16>{}); break;
+    case 128: body(std::integral_constant<int, 32>{}); break;
+    case 192: body(std::integral_constant<int, 48>{}); break;
+    case 256: body(std::integral_constant<int, 64>{}); break;
+    default: body(std::integral_constant<int, 96>{}); break;
   }
 }
 
@@ -457,12 +479,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   const int m = wk.x, c = wk.y & 0xffff;
   const float2* ys = y + sd.spec_off;
   constexpr int R = kSynBuffers;
+  // the input source is a compile-time choice, as in the float32 kernels
+  auto body = [&](auto ks_c) {
+    constexpr int KS = decltype(ks_c)::value;
+    if (staged & 2)
+      synthesis_body<KS, NP, R, true>(sd, m, c, ys, ring, spec);
+    else
+      synthesis_body<KS, NP, R, false>(sd, m, c, ys, ring, spec);
+  };
   switch (sd.g.kpad) {
-    case 64: synthesis_body<16, NP, R>(sd, m, c, ys, staged, ring, spec); break;
-    case 128: synthesis_body<32, NP, R>(sd, m, c, ys, staged, ring, spec); break;
-    case 192: synthesis_body<48, NP, R>(sd, m, c, ys, staged, ring, spec); break;
-    case 256: synthesis_body<64, NP, R>(sd, m, c, ys, staged, ring, spec); break;
-    default: synthesis_body<96, NP, R>(sd, m, c, ys, staged, ring, spec); break;
+    case 64: body(std::integral_constant<int, 16>{}); break;
+    case 128: body(std::integral_constant<int, 32>{}); break;
+    case 192: body(std::integral_constant<int, 48>{}); break;
+    case 256: body(std::integral_constant<int, 64>{}); break;
+    default: body(std::integral_constant<int, 96>{}); break;
   }
 }
 
