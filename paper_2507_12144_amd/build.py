@@ -2,6 +2,7 @@
 
     python -m paper_2507_12144_amd.build        # or build() from Python
     python -m paper_2507_12144_amd.build debug  # the race-check library
+    python -m paper_2507_12144_amd.build release debug asan   # all three
     python -m paper_2507_12144_amd.build asan   # host-sanitizer test build
 
 Every source is compiled with hipcc for --offload-arch=gfx950 with packed
@@ -26,11 +27,12 @@ FLAGS = [
 
 
 def sources():
-    """The HIP sources, the slowest to compile (the per-plane-count bf16
-    kernels, then the float32 contraction) first, so that the parallel build
-    ends soonest."""
+    """The HIP sources, the slowest to compile first (the three-plane bf16
+    kernels, the float32 contraction per NCB, then the other bf16 plane
+    counts), so that the parallel build ends soonest."""
     names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
-    order = lambda f: (0 if ("_np" in f or "_ncb" in f) else 1 if f.startswith("legendre") else 2, f)
+    heavy = ("_np3_", "_ncb", "_np2_", "_np1_")
+    order = lambda f: (next((i for i, h in enumerate(heavy) if h in f), len(heavy)), f)
     return [os.path.join(CSRC, f) for f in sorted(names, key=order)]
 
 
@@ -55,21 +57,30 @@ def _compile(src, build_dir, extra):
     return obj, err
 
 
-def build(verbose=False, variant="release"):
-    out, build_dir, extra = VARIANTS[variant]
-    os.makedirs(build_dir, exist_ok=True)
-    srcs = sources()
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(lambda src: _compile(src, build_dir, extra), srcs))
-    for obj, err in results:
+def build(verbose=False, variant="release", variants=None):
+    """Compile every source for each library variant named (``variants``, or
+    the one ``variant``) and link each; the compile jobs of all of them share
+    one pool, slowest first.  Returns the path of the last library."""
+    names = list(variants or [variant])
+    jobs = []
+    for src in sources():
+        for v in names:
+            out, build_dir, extra = VARIANTS[v]
+            os.makedirs(build_dir, exist_ok=True)
+            jobs.append((v, src, build_dir, extra))
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        results = list(ex.map(lambda j: (j[0],) + _compile(j[1], j[2], j[3]), jobs))
+    for _, obj, err in results:
         if verbose and err.strip():
             print(err, file=sys.stderr)
-    tmp = out + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, out)
+    for v in names:
+        out = VARIANTS[v][0]
+        tmp = out + ".tmp"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for w, o, _ in results if w == v]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed ({v}):\n{r.stderr}")
+        os.replace(tmp, out)
     return out
 
 
@@ -117,5 +128,9 @@ def build_host_asan():
 
 
 if __name__ == "__main__":
-    for v in (sys.argv[1:] or ["release"]):
-        print(build_host_asan() if v == "asan" else build(verbose=True, variant=v))
+    args = sys.argv[1:] or ["release"]
+    libs = [v for v in args if v != "asan"]
+    if libs:
+        print(build(verbose=True, variants=libs))
+    if "asan" in args:
+        print(build_host_asan())

@@ -496,22 +496,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
   }
 }
 
+// Launches of one plane count and direction, each explicitly instantiated
+// in a translation unit of its own (legendre_bf16_np{1,2,3}_{ana,syn}.hip),
+// so that the six compile in parallel.
 template <int NP>
-hipError_t launch_batched(bool analysis, const BatchArgs& b, const void* in, void* out, float c_rest,
-                          hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(8 * b.work_per));
-  if (analysis)
-    hipLaunchKernelGGL(analysis_batched<NP>, grid, dim3(256), 0, st, b.segs, b.work, b.work_per,
-                       static_cast<float2*>(out), c_rest, b.staged);
-  else
-    hipLaunchKernelGGL(synthesis_batched<NP>, grid, dim3(256), 0, st, b.segs, b.work, b.work_per,
-                       static_cast<const float2*>(in), b.staged);
+hipError_t launch_analysis(const BatchArgs& b, float2* y, float c_rest, hipStream_t st) {
+  hipLaunchKernelGGL(analysis_batched<NP>, dim3(static_cast<unsigned>(8 * b.work_per)), dim3(256), 0, st, b.segs,
+                     b.work, b.work_per, y, c_rest, b.staged);
   return hipGetLastError();
 }
 
-extern template hipError_t launch_batched<1>(bool, const BatchArgs&, const void*, void*, float, hipStream_t);
-extern template hipError_t launch_batched<2>(bool, const BatchArgs&, const void*, void*, float, hipStream_t);
-extern template hipError_t launch_batched<3>(bool, const BatchArgs&, const void*, void*, float, hipStream_t);
+template <int NP>
+hipError_t launch_synthesis(const BatchArgs& b, const float2* y, hipStream_t st) {
+  hipLaunchKernelGGL(synthesis_batched<NP>, dim3(static_cast<unsigned>(8 * b.work_per)), dim3(256), 0, st, b.segs,
+                     b.work, b.work_per, y, b.staged);
+  return hipGetLastError();
+}
+
+extern template hipError_t launch_analysis<1>(const BatchArgs&, float2*, float, hipStream_t);
+extern template hipError_t launch_analysis<2>(const BatchArgs&, float2*, float, hipStream_t);
+extern template hipError_t launch_analysis<3>(const BatchArgs&, float2*, float, hipStream_t);
+extern template hipError_t launch_synthesis<1>(const BatchArgs&, const float2*, hipStream_t);
+extern template hipError_t launch_synthesis<2>(const BatchArgs&, const float2*, hipStream_t);
+extern template hipError_t launch_synthesis<3>(const BatchArgs&, const float2*, hipStream_t);
 
 }  // namespace bf16p
 }  // namespace sht

@@ -68,19 +68,26 @@ def test_abi_host_asan_cpu():
     assert r.returncode == 0 and "cpu checks: 0 failure(s)" in out, out[-4000:]
 
 
+# Allocations by which the HIP runtime's own leftovers at exit have been
+# seen to differ between two runs of the same program.
+RUNTIME_JITTER = 3
+
+
 @pytest.mark.gpu
 def test_abi_host_asan_gpu(tmp_path):
-    """The GPU walk once and three times in one process.  The HIP runtime
-    keeps a fixed set of C++ allocations at exit that LeakSanitizer cannot
-    unwind (no frame pointers in the runtime) and so cannot suppress by
-    module; the library's own leaks would grow with the work done, so the
-    leak summary of the two runs must be the same."""
+    """The GPU walk once and six times in one process.  The HIP runtime
+    keeps a set of C++ allocations at exit that LeakSanitizer cannot unwind
+    (no frame pointers in the runtime) and so cannot suppress by module; its
+    size varies by an allocation or so from run to run.  The library's own
+    leaks would grow with the work done: a single allocation left behind per
+    walk adds five to the longer run, more than the runtime's variation."""
     assert os.path.exists(DRIVER), "tests/asan/abi_driver is not built: python -m paper_2507_12144_amd.build asan"
     leaks = []
-    for rep in (1, 3):
+    for rep in (1, 6):
         print(f"host asan driver, gpu mode x{rep}", flush=True)
-        r, out = _run(["gpu", str(tmp_path / f"tune{rep}.txt"), str(rep)], 240)
+        r, out = _run(["gpu", str(tmp_path / f"tune{rep}.txt"), str(rep)], 300)
         _no_memory_errors(out)
         assert "cpu+gpu checks: 0 failure(s)" in out, out[-4000:]
         leaks.append(_leaked(out))
-    assert leaks[0] == leaks[1], leaks
+    print("leaked (bytes, allocations), x1 / x6:", leaks, flush=True)
+    assert leaks[1][1] <= leaks[0][1] + RUNTIME_JITTER, leaks
