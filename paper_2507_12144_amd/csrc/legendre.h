@@ -37,6 +37,7 @@
 
 #include "internal.h"
 #include "kernel_common.h"
+#include "stage_waits.h"
 
 namespace sht {
 namespace fp32k {
@@ -130,8 +131,9 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
       as_global(sd.ystage + sd.ystage_off[m] + (static_cast<size_t>(p) * g.groups + (active ? cb : 0)) * nb * 256);
   if (nb > 0) {
     // Every stage issues the copies of stage s+2, past the end too, so that
-    // each wave always has exactly LPW copies in flight behind the ones it
-    // waits for and every wait is the same vm_lds_wait(LPW).
+    // each wave always has the copies of one stage in flight behind the ones
+    // it waits for (waits::analysis_behind: four while S / A streams in, LPW
+    // for the table stages).
     constexpr int XS = S::XS;
     if constexpr (S::XSTREAM) {
       // Stage u < XS: every wave copies rings lk * KS + 16u .. +15 of its
@@ -152,7 +154,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
         constexpr int u = decltype(u_c)::value;
         v4f* cur = ring_buf<u>(b0, b1, b2);
         v4f* nxt = ring_buf<u + 2>(b0, b1, b2);
-        __builtin_amdgcn_s_waitcnt(vm_lds_wait(u + 1 < XS ? S::LPWX : LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::analysis_behind(XS, LPW, 2, u)));
         stage_barrier();
         if constexpr (u + 2 < XS)
           issue_x(nxt, u + 2);
@@ -177,7 +179,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, co
         if (st >= nst) return false;
         v4f* cur = ring_buf<su + XS>(b0, b1, b2);
         v4f* nxt = ring_buf<su + XS + 2>(b0, b1, b2);
-        __builtin_amdgcn_s_waitcnt(vm_lds_wait(LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::analysis_behind(XS, LPW, 2, XS + su)));
         stage_barrier();
         issue_stage<SC, NW, LPW, PARTS, T4>(nxt, tab, nb, st + 2, wave, lane);
         const int ib = st / PARTS;
@@ -305,19 +307,12 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
   for (int rb = 0; rb < KR; ++rb) acc[rb] = floatx4{0.f, 0.f, 0.f, 0.f};
   if (nb > 0) {
     // Stage u issues the table copies of stage u+2 and, at part 1, the
-    // spectrum copies of the next row block (4 per wave): with two parts
-    // before the table copies (part 0, right after, then waits for all but
-    // one stage's copies instead of all of them), with three after them (the
-    // gathered spectrum then does not hold up the table copies).  Behind the
-    // table copies of stage s (issued at stage s-2) come those of stage s+1,
-    // the spectrum copies of stage s-1 if at part 1, and, issued after, those
-    // of stage s-2 if at part 1.  At part 0 the spectrum copies of part 1 of
-    // the previous row block must be complete too: only the table copies of
-    // the PARTS-2 stages after it, and of that stage itself if issued after,
-    // follow them.  The prologue plays stages -2 and -1 the same way (stage
-    // -2 is at part 1 with three parts, stage -1 with two).
+    // spectrum copies of the next row block (4 per wave), in the order
+    // waits::spec_first gives; waits::synthesis_behind counts the copies each
+    // stage may leave in flight.  The prologue plays stages -2 and -1 the
+    // same way (stage -2 is at part 1 with three parts, stage -1 with two).
     static_assert(PARTS == 2 || PARTS == 3, "spectrum refill at part 1");
-    constexpr bool SF = PARTS == 2;  // spectrum copies first at part 1
+    constexpr bool SF = waits::spec_first(PARTS);
     issue_stage<SC, NW, LPW, PARTS, T4>(b0, tab, nb, 0, wave, lane);
     spec_copy(0);
     issue_stage<SC, NW, LPW, PARTS, T4>(b1, tab, nb, 1, wave, lane);
@@ -330,11 +325,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         if (st >= nst) return false;
         v4f* cur = ring_buf<su>(b0, b1, b2);
         v4f* nxt = ring_buf<su + 2>(b0, b1, b2);
-        constexpr int pm2 = (part + 2 * PARTS - 2) % PARTS, pm1 = (part + PARTS - 1) % PARTS;
-        constexpr int behind = LPW + (pm1 == 1 ? 4 : 0) + (!SF && pm2 == 1 ? 4 : 0);
-        constexpr int spec_behind = (SF ? PARTS - 1 : PARTS - 2) * LPW;
-        constexpr int need = (part == 0 && spec_behind < behind) ? spec_behind : behind;
-        __builtin_amdgcn_s_waitcnt(vm_lds_wait(need));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::synthesis_behind(PARTS, LPW, 2, 4, su)));
         stage_barrier();
         const int ib = st / PARTS;
         if constexpr (part == 0) {

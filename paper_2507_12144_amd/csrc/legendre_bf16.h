@@ -35,6 +35,7 @@
 #include "bf16.h"
 #include "internal.h"
 #include "kernel_common.h"
+#include "stage_waits.h"
 
 namespace sht {
 namespace bf16p {
@@ -135,41 +136,6 @@ __device__ __forceinline__ void issue_stage(v4f* B, const uint16_t* __restrict__
 
 __device__ __forceinline__ bf16x8 as_bf16x8(v4f v) { return __builtin_bit_cast(bf16x8, v); }
 
-// Copies per wave in flight behind global analysis stage gs: those of
-// stages gs+1 .. gs+D-1 (four for a stage of S / A, LPW for a table stage).
-template <int XS, int LPW, int D>
-constexpr int x_behind(int gs) {
-  int n = 0;
-  for (int i = 1; i < D; ++i) n += (gs + i < XS) ? 4 : LPW;
-  return n;
-}
-
-// Synthesis: stage j issues the table copies of stage j+D and, at part 1,
-// the NB spectrum copies of the next row block: before the table copies when
-// a row block has two parts (part 0, right after, then waits for all but
-// one stage's copies instead of all of them), after them otherwise (the
-// gathered spectrum then does not hold up the table copies).
-constexpr bool spec_first(int parts) { return parts == 2; }
-
-// Copies in flight that synthesis stage s may leave outstanding.  Behind the
-// table copies of stage s (issued at stage s-D) come those of stages s+1 ..
-// s+D-1 and the spectrum copies of the stages at part 1 among s-D+1 .. s-1,
-// and among s-D too if issued after the table copies; a stage at part 0
-// also needs the spectrum copies issued at part 1 of the previous row block,
-// which only the table copies of the PARTS-2 stages after that stage, and
-// of that stage itself if issued after, follow.
-template <int PARTS, int LPW, int D, int NB>
-constexpr int s_behind(int s) {
-  constexpr bool sf = spec_first(PARTS);
-  int n = (D - 1) * LPW;
-  for (int j = sf ? s - D + 1 : s - D; j < s; ++j)
-    if (((j % PARTS) + PARTS) % PARTS == 1) n += NB;
-  const int ns = (sf ? PARTS - 1 : PARTS - 2) * LPW;
-  if (s % PARTS == 0 && ns < n) n = ns;
-  return n;
-}
-
-
 // Analysis.  Contraction index k of a wave's K slice = lk * KS + 8t + e for
 // lane group lk, step t (K = 32: 8 values a lane) and element e.  Global
 // stage g < XS brings rings 16g .. 16g+15 of every lane group's K slice of
@@ -228,7 +194,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
     });
     unrolled<0, XS>([&](auto u_c) {
       constexpr int u = decltype(u_c)::value;
-      __builtin_amdgcn_s_waitcnt(vm_lds_wait(x_behind<XS, LPW, D>(u)));
+      __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::analysis_behind(XS, LPW, D, u)));
       stage_barrier();
       issue(std::integral_constant<int, u + D>{}, u + D - XS);
       const float* xb = reinterpret_cast<const float*>(rbuf<u, NBUF>(ring)) + (4 * wave + lk) * 256 + li;
@@ -247,7 +213,7 @@ __device__ __forceinline__ void analysis_body(const SegDev& sd, int m, int c, fl
         constexpr int part = su % PARTS;
         const int st = st0 + su;
         if (st >= nst) return false;
-        __builtin_amdgcn_s_waitcnt(vm_lds_wait((D - 1) * LPW));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::analysis_behind(XS, LPW, D, XS + su)));
         stage_barrier();
         issue(std::integral_constant<int, XS + su + D>{}, st + D);
         const v4f* cur = rbuf<XS + su, NBUF>(ring);
@@ -372,7 +338,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
     // of stage v+D and the spectrum of row block 0 where v is at part 1, in
     // the loop's order); when none of them is at part 1, row block 0's
     // spectrum goes first.
-    constexpr bool SF = spec_first(PARTS);
+    constexpr bool SF = waits::spec_first(PARTS);
     if constexpr (PARTS > D + 1) spec_copy(0);
     unrolled<0, D>([&](auto i_c) {
       constexpr int i = decltype(i_c)::value;
@@ -390,7 +356,7 @@ __device__ __forceinline__ void synthesis_body(const SegDev& sd, int m, int c, c
         constexpr int part = su % PARTS;
         const int st = st0 + su;
         if (st >= nst) return false;
-        __builtin_amdgcn_s_waitcnt(vm_lds_wait(s_behind<PARTS, LPW, D, NB>(su)));
+        __builtin_amdgcn_s_waitcnt(vm_lds_wait(waits::synthesis_behind(PARTS, LPW, D, NB, su)));
         stage_barrier();
         const int ib = st / PARTS;
         if constexpr (part == 0) {
